@@ -1,0 +1,185 @@
+/*
+ * nlf.h -- C ABI of the MI355X (gfx950) library for nonlocal potentials of the nonlinear
+ * Schroedinger equation evaluated through the nonuniform FFT, and the ground-state and
+ * dynamics solvers built on it.
+ *
+ * Method (Bao, Jiang, Tang, Zhang, "Computing the ground state and dynamics of the NLSE
+ * with nonlocal interactions via the nonuniform FFT"):
+ *   u = U * rho = (2 pi)^-d int Uhat(k) rhohat(k) e^{i k.x} dk            (Sec. 2, Eq. 'nonlocal53')
+ * truncated to the ball |k| <= P and written in spherical/polar coordinates, where the
+ * Jacobian |k|^(d-1) cancels the Coulomb symbol (Sec. 2.1, Eq. 'ifft').  The quadrature sum
+ * is evaluated with a type-2 NUFFT (grid -> Fourier nodes), a pointwise symbol-times-weight
+ * multiply, and a type-1 NUFFT (nodes -> grid).  The 2D Laplace kernel has a stronger
+ * singularity and is handled by subtracting a Gaussian with the density's first two moments
+ * (Sec. 2.2, Alg. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Grid: box [-L_0,L_0) x ... , n_i points per axis, x_j = -L_i + j h_i, h_i = 2 L_i / n_i,
+ *    row-major (C order): the LAST axis is contiguous.  n_i must be a power of two in [8, 1024].
+ *  * Precision: a plan is FP64 (NLF_F64) or FP32 (NLF_F32).  Every bulk array handed to the
+ *    library (densities, potentials, node values, wave functions) has the plan's precision;
+ *    complex arrays are interleaved (re, im).  Quadrature weights, the symbol, the Laplace
+ *    subtraction and all reductions are FP64 in both precisions.
+ *  * Memory: every pointer argument named *_dev is device memory owned by the caller, valid for
+ *    the duration of the call's stream work; the library never frees caller memory.  Plans own
+ *    their workspaces (allocated in nlf_plan_create, freed in nlf_plan_destroy).
+ *  * Streams: all device work of a plan is enqueued on the HIP stream given at plan creation
+ *    (NULL = the default stream).  Calls return when the work is enqueued unless stated
+ *    otherwise; the solvers synchronise the stream to read convergence flags.
+ *  * Concurrency: a plan is not re-entrant; use one plan per stream.
+ *  * Errors: every call returns an int status; 0 is success, negative values are errors.
+ *    nlf_last_error() returns a message for the calling thread's last error.  No C++
+ *    exception crosses this boundary.
+ *  * Batching: a plan with opts.batch = B processes B independent fields per call; arrays are
+ *    laid out batch-major ([B][...]).
+ */
+#ifndef NLF_H
+#define NLF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------- */
+#define NLF_OK            0
+#define NLF_EINVAL       -1   /* NULL pointer, bad size, inconsistent argument            */
+#define NLF_EUNSUPPORTED -2   /* dimension not 2/3, n_i not a power of two in [8,1024], ... */
+#define NLF_ENOMEM       -3   /* device or host allocation failed                          */
+#define NLF_EHIP         -4   /* HIP runtime error (message kept for nlf_last_error)       */
+#define NLF_ENOCONV      -5   /* iteration cap reached; statistics are still filled        */
+#define NLF_ENONFINITE   -6   /* a NaN/Inf was detected in a reduction                      */
+
+/* ---- enums ---------------------------------------------------------------------------- */
+#define NLF_F64 0
+#define NLF_F32 1
+
+/* Interaction kernels (Sec. 1, Eqs. 'Kernal' and 'Kernal21d').                            */
+#define NLF_COULOMB3D 1   /* U = 1/(4 pi |x|),     Uhat = 1/|k|^2, d = 3                    */
+#define NLF_COULOMB2D 2   /* U = 1/(2 pi |x|),     Uhat = 1/|k|,   d = 2                    */
+#define NLF_LAPLACE2D 3   /* U = -ln|x| / (2 pi),  Uhat = 1/|k|^2, d = 2 (Gaussian subtraction) */
+
+/* ---- plan ----------------------------------------------------------------------------- */
+typedef struct {
+    int    dim;      /* 2 or 3                                                               */
+    int    n[3];     /* grid points per axis (n[2] ignored in 2D)                             */
+    double L[3];     /* half-widths: axis i spans [-L_i, L_i)                                 */
+} nlf_box;
+
+/* Plan options.  Any field left 0 takes its default.                                        */
+typedef struct {
+    int    prec;     /* NLF_F64 (default) or NLF_F32                                          */
+    int    n_r;      /* radial Gauss-Legendre nodes on [0,P]        (default n[0])             */
+    int    n_theta;  /* Gauss-Legendre nodes in cos(theta), 3D only (default n[0])             */
+    int    n_phi;    /* trapezoid nodes in the azimuth, even        (default 2 n[0])           */
+    double P;        /* Fourier cutoff radius                       (default pi / max_i h_i)   */
+    double sigma;    /* Laplace subtraction width                   (default 6 sqrt(2) / P)    */
+    int    msp;      /* Gaussian half-width in oversampled cells    (default 12 FP64, 7 FP32)  */
+    int    batch;    /* independent fields per call                 (default 1)                */
+} nlf_opts;
+
+typedef struct nlf_plan nlf_plan;
+
+/* Facts about a built plan, for callers that size their buffers.                            */
+typedef struct {
+    int    dim, kernel, prec, batch, msp;
+    int    n[3];
+    double L[3], h[3];
+    double P, sigma;
+    long long n_grid;      /* prod n_i                                                       */
+    long long n_nodes;     /* M = n_r n_theta n_phi (3D) or n_r n_phi (2D), the full node set  */
+    long long n_half;      /* M / 2 nodes actually evaluated (the other half by symmetry)      */
+    long long workspace_bytes;
+} nlf_plan_info;
+
+/* Create a plan for the potential of `kernel` on `box` (Sec. 2.1 nodes and weights, Eq.
+ * 'ifft').  Builds the node tables on the host in FP64, sorts the nodes into bins of the
+ * oversampled grid, uploads them and allocates the workspace.  `stream` is a hipStream_t.
+ * Returns NLF_EUNSUPPORTED for a dimension/kernel mismatch or a non-power-of-two grid.     */
+int nlf_plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* stream,
+                    nlf_plan** out);
+int nlf_plan_destroy(nlf_plan* plan);
+int nlf_plan_get_info(const nlf_plan* plan, nlf_plan_info* info);
+
+/* Quadrature nodes of the plan in canonical order (radial index slowest, then polar in 3D,
+ * then azimuth fastest): k_host receives M*dim doubles (k_m components in grid-axis order),
+ * w_host receives M doubles, the weight of d|k| dphi (2D) or d|k| dmu dphi (3D) without the
+ * Jacobian (Sec. 2.1, Eq. 'ifft').  Host memory owned by the caller; either may be NULL.    */
+int nlf_plan_nodes(const nlf_plan* plan, double* k_host, double* w_host);
+
+/* u = U * rho on the grid (Sec. 2.1 Eq. 'ifft'; for NLF_LAPLACE2D Sec. 2.2 Alg. 1).
+ * rho_dev: [batch][n] real; u_dev: [batch][n] real; plan precision; may not alias.        */
+int nlf_potential(nlf_plan* plan, const void* rho_dev, void* u_dev);
+
+/* Type-2 stage alone: rhohat_m = (prod h_i) sum_j rho_j e^{-i k_m . x_j} at all M nodes in
+ * canonical order (the trapezoid transform of the grid data, Alg. 1 first step).
+ * rho_dev: [batch][n] real; rhohat_dev: [batch][M] complex; plan precision.              */
+int nlf_type2(nlf_plan* plan, const void* rho_dev, void* rhohat_dev);
+
+/* Type-1 stage alone: u_j = Re sum_m c_m e^{+i k_m . x_j} over all M nodes in canonical
+ * order (the final sum of Eq. 'ifft' once the symbol and weights are applied).
+ * c_dev: [batch][M] complex; u_dev: [batch][n] real; plan precision.                     */
+int nlf_type1(nlf_plan* plan, const void* c_dev, void* u_dev);
+
+/* ---- solvers -------------------------------------------------------------------------- */
+/* Physical parameters: V = (1/2) sum_i gamma_i^2 x_i^2 unless V_dev != NULL, in which case
+ * V_dev ([n] real FP64, device) is used.  beta is the interaction constant of Eq. 'sps-eq'. */
+typedef struct {
+    double      beta;
+    double      gamma[3];
+    const void* V_dev;
+} nlf_phys;
+
+/* Gradient-flow options (Sec. 3.1/3.2).  tau: time step (default 1e-2); eps0: stopping
+ * tolerance on max|phi^{n+1}-phi^n|/tau (default 1e-10); max_iter (default 100000);
+ * check_every: outer steps between host convergence checks (default 10);
+ * cg_tol: relative residual of the inner linear solve (default 1e-13 FP64, 1e-7 FP32).      */
+typedef struct {
+    double tau, eps0;
+    int    max_iter, check_every;
+    double cg_tol;
+    int    cg_max_iter;
+} nlf_gf_opts;
+
+typedef struct {
+    int    iters;           /* outer gradient-flow steps taken                              */
+    int    cg_iters;        /* inner linear-solver iterations, summed                       */
+    double E, mu, Ekin, Epot, Eint;
+    double residual;        /* last max|phi^{n+1}-phi^n|/tau                                 */
+    double virial;          /* 2E_kin - 2E_pot + (E_int | beta/(4 pi)), Sec. 3.2             */
+    double mass;            /* h^d sum |phi|^2                                               */
+} nlf_gs_stats;
+
+/* Ground state by the backward-Euler normalized gradient flow, Fourier pseudospectral in
+ * space, potential by this plan (Sec. 3.1, Eqs. 'gf-eq2'-'gffg33').  The linear part is
+ * implicit: (1/tau - Delta/2 + V + beta varphi^n) phi1 = phi^n / tau, solved by conjugate
+ * gradients preconditioned with the inverse of (1/tau + alpha + |mu|^2/2) in Fourier space.
+ * psi0_dev: [batch][n] real initial guess or NULL (harmonic-oscillator Gaussian);
+ * psi_dev: [batch][n] real output; stats: host array of `batch` entries.
+ * Returns NLF_ENOCONV if any field hit max_iter (stats still filled).                       */
+int nlf_ground_state(nlf_plan* plan, const nlf_phys* phys, const nlf_gf_opts* gf,
+                     const void* psi0_dev, void* psi_dev, nlf_gs_stats* stats);
+
+/* Time-splitting pseudospectral dynamics (Sec. 4.1, Eqs. 'sps-eq65'-'sps-eq68').
+ * order 2: Strang K(dt/2) P(dt) K(dt/2); order 4: Yoshida composition of three Strang steps.
+ * psi_dev: [batch][n] complex, in/out.  diag_host: if non-NULL, receives (mass, energy) per
+ * field every diag_every steps and at step 0: 2 * batch * (nsteps/diag_every + 1) doubles.   */
+typedef struct {
+    double dt;
+    int    nsteps, order, diag_every;
+} nlf_ts_opts;
+
+int nlf_evolve(nlf_plan* plan, const nlf_phys* phys, const nlf_ts_opts* ts, void* psi_dev,
+               double* diag_host);
+
+/* Message for the calling thread's last error ("" if none).                                 */
+const char* nlf_last_error(void);
+/* Static description of a status code.                                                      */
+const char* nlf_strerror(int status);
+/* Library version string.                                                                    */
+const char* nlf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLF_H */

@@ -1,0 +1,513 @@
+// Hand-written Stockham FFT for gfx950, used on the 2x-oversampled NUFFT grid and on the
+// solver grid.  One workgroup transforms a block of lines held in LDS (radix-4 passes plus one
+// radix-2 pass for odd log2 n).  Two kernels:
+//   k_fft_rows : lines along the contiguous (last) axis.  Optional fused prologue/epilogue:
+//                real density in -> precorrect (divide by the Gaussian's Fourier coefficients)
+//                and zero-pad into the oversampled line (type-2 NUFFT input), and
+//                oversampled line -> truncate, postcorrect, real part (+ the analytic u1 term of
+//                the 2D Laplace kernel) -> potential out (type-1 NUFFT output).
+//   k_fft_cols : lines along a strided axis, C adjacent columns per workgroup so each row
+//                segment is a contiguous load; optional pruning of the zero rows on load (the
+//                padded half of the type-2 input) and of the unused rows on store (the half of the
+//                type-1 output that is cut away).
+// The NUFFT sums these feed are those of Sec. 2.1, Eq. 'ifft'.
+#include <algorithm>
+#include <cmath>
+
+#include "nlf_internal.h"
+
+namespace nlf {
+
+template <typename T> __device__ __forceinline__ V2<T> mk(T x, T y);
+template <> __device__ __forceinline__ float2 mk<float>(float x, float y) { return make_float2(x, y); }
+template <> __device__ __forceinline__ double2 mk<double>(double x, double y) { return make_double2(x, y); }
+
+template <typename T> __device__ __forceinline__ V2<T> cadd(V2<T> a, V2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ V2<T> csub(V2<T> a, V2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ V2<T> cmul(V2<T> a, V2<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Elements held in LDS per workgroup (128 KiB in both precisions) and threads per workgroup:
+// every thread owns 4 radix-4 (or 8 radix-2) butterflies per pass.
+template <typename T> struct FftCfg;
+template <> struct FftCfg<double> { static constexpr int E = 8192, NT = 512; };
+template <> struct FftCfg<float>  { static constexpr int E = 16384, NT = 1024; };
+
+// data index j (0..nd-1, x_j = -L + j h) -> row of the 2x oversampled periodic grid holding
+// centred frequency/position j - nd/2
+__device__ __forceinline__ int dmap(int j, int nd, int Mr) {
+    int c = j - nd / 2;
+    return c < 0 ? c + Mr : c;
+}
+__device__ __forceinline__ bool is_data_row(int r, int nd, int Mr) { return r < nd / 2 || r >= Mr - nd / 2; }
+
+// In-place multi-line Stockham FFT of nl lines of length n = 2^lg held in buf[line*pitch + i].
+// tw[t] = exp(-2 pi i t / n).  DIR = -1 forward, +1 inverse (unnormalised).
+template <typename T, int DIR>
+__device__ void lds_fft(V2<T>* buf, int pitch, int n, int lg, int nl, const V2<T>* __restrict__ tw) {
+    constexpr int NT = FftCfg<T>::NT;
+    constexpr int RB = FftCfg<T>::E / (4 * NT);   // radix-4 butterflies per thread
+    const int tid = threadIdx.x;
+    int p = 1;
+    if (lg & 1) {
+        const int h = n >> 1;
+        const int tot = nl * h;
+        V2<T> y0[2 * RB], y1[2 * RB];
+#pragma unroll
+        for (int r = 0; r < 2 * RB; ++r) {
+            int idx = tid + r * NT;
+            if (idx < tot) {
+                int line = idx / h, i = idx - line * h;
+                V2<T>* x = buf + line * pitch;
+                V2<T> a0 = x[i], a1 = x[i + h];
+                y0[r] = cadd<T>(a0, a1);
+                y1[r] = csub<T>(a0, a1);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2 * RB; ++r) {
+            int idx = tid + r * NT;
+            if (idx < tot) {
+                int line = idx / h, i = idx - line * h;
+                V2<T>* x = buf + line * pitch;
+                x[2 * i] = y0[r];
+                x[2 * i + 1] = y1[r];
+            }
+        }
+        __syncthreads();
+        p = 2;
+    }
+    const int q = n >> 2;
+    const int tot = nl * q;
+    while (p < n) {
+        V2<T> y[RB][4];
+        const int tstep = n / (4 * p);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            int idx = tid + r * NT;
+            if (idx < tot) {
+                int line = idx / q, i = idx - line * q;
+                int k = i & (p - 1);
+                V2<T>* x = buf + line * pitch;
+                V2<T> a0 = x[i], a1 = x[i + q], a2 = x[i + 2 * q], a3 = x[i + 3 * q];
+                if (p > 1) {
+                    V2<T> w1 = tw[k * tstep], w2 = tw[2 * k * tstep], w3 = tw[3 * k * tstep];
+                    if (DIR > 0) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+                    a1 = cmul<T>(a1, w1);
+                    a2 = cmul<T>(a2, w2);
+                    a3 = cmul<T>(a3, w3);
+                }
+                V2<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2), t2 = cadd<T>(a1, a3), t3 = csub<T>(a1, a3);
+                y[r][0] = cadd<T>(t0, t2);
+                y[r][2] = csub<T>(t0, t2);
+                if (DIR < 0) {
+                    y[r][1] = mk<T>(t1.x + t3.y, t1.y - t3.x);
+                    y[r][3] = mk<T>(t1.x - t3.y, t1.y + t3.x);
+                } else {
+                    y[r][1] = mk<T>(t1.x - t3.y, t1.y + t3.x);
+                    y[r][3] = mk<T>(t1.x + t3.y, t1.y - t3.x);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            int idx = tid + r * NT;
+            if (idx < tot) {
+                int line = idx / q, i = idx - line * q;
+                int k = i & (p - 1);
+                int j = (i - k) * 4 + k;
+                V2<T>* x = buf + line * pitch;
+                x[j] = y[r][0];
+                x[j + p] = y[r][1];
+                x[j + 2 * p] = y[r][2];
+                x[j + 3 * p] = y[r][3];
+            }
+        }
+        __syncthreads();
+        p *= 4;
+    }
+}
+
+// ---- contiguous-axis kernel ---------------------------------------------------------------------
+enum { LOAD_GRID = 0, LOAD_RHO = 1 };
+enum { STORE_GRID = 0, STORE_U = 1 };
+
+struct RowsArgs {
+    void* grid;            // complex lines of length n
+    long long gstride;     // batch stride of grid (elements)
+    const void* rho;       // LOAD_RHO: real data [batch][N]
+    void* u;               // STORE_U: real output [batch][N]
+    long long rstride;     // batch stride of rho / u (elements)
+    int n, lg;             // FFT length along the last axis and log2
+    int nlines;            // active lines per batch field
+    int lines_per_wg;
+    int dim;
+    int nd[3], Mr[3];      // data and oversampled sizes (for the mapped modes)
+    const double* dec0; const double* dec1; const double* dec2;  // 1/c_g per axis (mapped modes)
+    const void* tw;
+    double post;           // output scale (STORE_U)
+    // 2D Laplace: u += m0 u11 - m1 . u12 (Sec. 2.2, Eqs. 'phi1_exct', 'phi12_ext')
+    int add_u1;
+    const double* mom;     // [batch][4]: m0, m1x, m1y
+    double sigma, L0, L1, h0, h1;
+};
+
+// E1(z) + ln z for z >= 0: the series -gamma - sum_{n>=1} (-z)^n/(n n!) below 1 (Abramowitz &
+// Stegun 5.1.11) and the continued fraction of E1 above (A&S 5.1.22, evaluated by the modified
+// Lentz method).  Smooth at z = 0 where it equals -gamma.
+__device__ double e1_plus_log(double z) {
+    const double egamma = 0.57721566490153286061;
+    if (z < 1.0) {
+        double term = 1.0, sum = 0.0;
+        for (int k = 1; k < 40; ++k) {
+            term *= -z / k;
+            double t = term / k;
+            sum += t;
+            if (fabs(t) < 1e-18 * fabs(sum) + 1e-300) break;
+        }
+        return -egamma - sum;
+    }
+    const double tiny = 1e-300;
+    double b = z + 1.0, c = 1.0 / tiny, d = 1.0 / b, hh = d;
+    for (int i = 1; i < 200; ++i) {
+        double an = -(double)i * i;
+        b += 2.0;
+        d = 1.0 / (an * d + b);
+        c = b + an / c;
+        double del = c * d;
+        hh *= del;
+        if (fabs(del - 1.0) < 1e-17) break;
+    }
+    return hh * exp(-z) + log(z);
+}
+
+template <typename T, int DIR, int LOAD, int STORE>
+__global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    constexpr int NT = FftCfg<T>::NT;
+    const int n = a.n;
+    const int pitch = n;
+    const int b = blockIdx.y;
+    const int line0 = blockIdx.x * a.lines_per_wg;
+    const int nl = min(a.lines_per_wg, a.nlines - line0);
+    V2<T>* grid = reinterpret_cast<V2<T>*>(a.grid) + (long long)b * a.gstride;
+    const bool mapped = (LOAD == LOAD_RHO) || (STORE == STORE_U);
+    const int last = a.dim - 1;
+    const int ndl = a.nd[last];
+
+    // grid line index and the per-line deconvolution factor of line (line0 + l)
+    auto grid_line = [&](int l, double* fac, int* j0o, int* j1o) -> long long {
+        int al = line0 + l;
+        if (!mapped) return al;
+        if (a.dim == 2) {
+            *j0o = al; *j1o = 0;
+            *fac = a.dec0[al];
+            return dmap(al, a.nd[0], a.Mr[0]);
+        }
+        int j0 = al / a.nd[1], j1 = al - j0 * a.nd[1];
+        *j0o = j0; *j1o = j1;
+        *fac = a.dec0[j0] * a.dec1[j1];
+        return (long long)dmap(j0, a.nd[0], a.Mr[0]) * a.Mr[1] + dmap(j1, a.nd[1], a.Mr[1]);
+    };
+    const double* decl = (a.dim == 2) ? a.dec1 : a.dec2;
+
+    // ---- load
+    if (LOAD == LOAD_RHO) {
+        const T* rho = reinterpret_cast<const T*>(a.rho) + (long long)b * a.rstride;
+        for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
+            int l = idx / n, c = idx - l * n;
+            double fac = 1;
+            int j0 = 0, j1 = 0;
+            (void)grid_line(l, &fac, &j0, &j1);
+            // oversampled position c holds data index j with dmap(j) == c, if any
+            V2<T> v = mk<T>(0, 0);
+            if (is_data_row(c, ndl, n)) {
+                int j = (c < ndl / 2) ? c + ndl / 2 : c - (n - ndl / 2);
+                long long src = (long long)(line0 + l) * ndl + j;
+                v.x = (T)((double)rho[src] * fac * decl[j]);
+            }
+            buf[l * pitch + c] = v;
+        }
+    } else {
+        for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
+            int l = idx / n, c = idx - l * n;
+            double fac;
+            int j0, j1;
+            long long gl = grid_line(l, &fac, &j0, &j1);
+            buf[l * pitch + c] = grid[gl * n + c];
+        }
+    }
+    __syncthreads();
+    lds_fft<T, DIR>(buf, pitch, n, a.lg, nl, reinterpret_cast<const V2<T>*>(a.tw));
+
+    // ---- store
+    if (STORE == STORE_GRID) {
+        for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
+            int l = idx / n, c = idx - l * n;
+            double fac;
+            int j0, j1;
+            long long gl = grid_line(l, &fac, &j0, &j1);
+            grid[gl * n + c] = buf[l * pitch + c];
+        }
+    } else {
+        T* u = reinterpret_cast<T*>(a.u) + (long long)b * a.rstride;
+        double m0 = 0, m1x = 0, m1y = 0;
+        if (a.add_u1) {
+            m0 = a.mom[4 * b + 0];
+            m1x = a.mom[4 * b + 1];
+            m1y = a.mom[4 * b + 2];
+        }
+        const double inv4pi = 0.07957747154594766788;   // 1/(4 pi)
+        const double ln2s2 = log(2.0 * a.sigma * a.sigma);
+        for (int idx = threadIdx.x; idx < nl * ndl; idx += NT) {
+            int l = idx / ndl, j = idx - l * ndl;
+            double fac;
+            int j0, j1;
+            (void)grid_line(l, &fac, &j0, &j1);
+            int c = dmap(j, ndl, n);
+            double val = (double)buf[l * pitch + c].x * fac * decl[j] * a.post;
+            if (a.add_u1) {
+                // 2D only: line = row j0, element j = column index
+                double x = -a.L0 + j0 * a.h0, y = -a.L1 + j * a.h1;
+                double r2 = x * x + y * y;
+                double z = r2 / (2.0 * a.sigma * a.sigma);
+                double u11 = -inv4pi * (e1_plus_log(z) + ln2s2);
+                double f = (r2 > 0) ? -(-expm1(-z)) / (2.0 * 3.14159265358979323846 * r2) : 0.0;
+                val += m0 * u11 - (m1x * f * x + m1y * f * y);
+            }
+            u[(long long)(line0 + l) * ndl + j] = (T)val;
+        }
+    }
+}
+
+// ---- strided-axis kernel ----------------------------------------------------------------------
+struct ColsArgs {
+    void* grid;
+    long long gstride;      // batch stride (elements)
+    int n, lg;              // FFT length along this axis
+    long long inner;        // elements between consecutive rows of a line (product of later axes)
+    int C;                  // adjacent columns per workgroup (divides inner)
+    int ncb;                // column blocks per outer index = inner / C
+    int outer_mapped;       // 1: outer index o is a data index of the previous axis (pruned)
+    int outer_nd, outer_Mr;
+    int nd;                 // data count along this axis (for pruning)
+    const void* tw;
+};
+
+template <typename T, int DIR, bool LPRUNE, bool SPRUNE>
+__global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_cols(ColsArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    constexpr int NT = FftCfg<T>::NT;
+    const int n = a.n, C = a.C;
+    const int pitch = n + 1;
+    // XCD-aware order: consecutive hardware workgroup ids go round-robin over the 8 XCDs; give
+    // each XCD a contiguous range of column blocks so neighbouring row segments share its L2.
+    int cb = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) cb = (cb & 7) * (nb >> 3) + (cb >> 3);
+    int o = blockIdx.y;
+    long long go = a.outer_mapped ? dmap(o, a.outer_nd, a.outer_Mr) : o;
+    V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride +
+                  go * (long long)n * a.inner + (long long)cb * C;
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
+        int r = idx / C, c = idx - r * C;
+        V2<T> v = mk<T>(0, 0);
+        if (!LPRUNE || is_data_row(r, a.nd, n)) v = base[(long long)r * a.inner + c];
+        buf[c * pitch + r] = v;
+    }
+    __syncthreads();
+    lds_fft<T, DIR>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
+        int r = idx / C, c = idx - r * C;
+        if (!SPRUNE || is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
+    }
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* p, long long count) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < count; i += st) p[i] = (T)0;
+}
+
+// ---- host launchers ---------------------------------------------------------------------------
+static int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+template <typename T, int DIR, int LOAD, int STORE>
+static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
+    constexpr int E = FftCfg<T>::E, NT = FftCfg<T>::NT;
+    a.lg = ilog2(a.n);
+    a.lines_per_wg = std::max(1, E / a.n);
+    if (a.n > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
+    dim3 grid((a.nlines + a.lines_per_wg - 1) / a.lines_per_wg, batch);
+    size_t lds = (size_t)a.lines_per_wg * a.n * sizeof(V2<T>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, DIR, LOAD, STORE>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fft_rows<T, DIR, LOAD, STORE>), grid, dim3(NT), lds, p->stream, a);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+template <typename T, int DIR, bool LP, bool SP>
+static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
+    constexpr int E = FftCfg<T>::E, NT = FftCfg<T>::NT;
+    a.lg = ilog2(a.n);
+    int C = 16;
+    while (C > 1 && (C * (a.n + 1) > E || a.inner % C)) C >>= 1;
+    if (a.n + 1 > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
+    a.C = C;
+    a.ncb = (int)(a.inner / C);
+    dim3 grid(a.ncb, outer, batch);
+    size_t lds = (size_t)C * (a.n + 1) * sizeof(V2<T>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP>), grid, dim3(NT), lds, p->stream, a);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+template <typename T>
+static int type2_forward_t(nlf_plan* p, const void* rho) {
+    const int d = p->dim;
+    RowsArgs r{};
+    r.grid = p->grid_a;
+    r.gstride = p->G;
+    r.rho = rho;
+    r.rstride = p->N;
+    r.n = p->Mr[d - 1];
+    r.dim = d;
+    for (int i = 0; i < 3; ++i) { r.nd[i] = p->n[i]; r.Mr[i] = p->Mr[i]; }
+    r.dec0 = p->dec[0];
+    r.dec1 = p->dec[1];
+    r.dec2 = p->dec[2];
+    r.tw = p->tw_big[d - 1];
+    r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
+    NLF_TRY((launch_rows<T, -1, LOAD_RHO, STORE_GRID>(p, r, p->batch)));
+    if (d == 2) {
+        ColsArgs c{};
+        c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[0]; c.inner = p->Mr[1];
+        c.nd = p->n[0]; c.tw = p->tw_big[0];
+        NLF_TRY((launch_cols<T, -1, true, false>(p, c, 1, p->batch)));
+    } else {
+        ColsArgs c{};
+        c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
+        c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
+        c.nd = p->n[1]; c.tw = p->tw_big[1];
+        NLF_TRY((launch_cols<T, -1, true, false>(p, c, p->n[0], p->batch)));
+        ColsArgs c0{};
+        c0.grid = p->grid_a; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
+        c0.nd = p->n[0]; c0.tw = p->tw_big[0];
+        NLF_TRY((launch_cols<T, -1, true, false>(p, c0, 1, p->batch)));
+    }
+    return NLF_OK;
+}
+
+template <typename T>
+static int type1_inverse_t(nlf_plan* p, void* u, bool add_u1) {
+    const int d = p->dim;
+    if (d == 2) {
+        ColsArgs c{};
+        c.grid = p->grid_b; c.gstride = p->G; c.n = p->Mr[0]; c.inner = p->Mr[1];
+        c.nd = p->n[0]; c.tw = p->tw_big[0];
+        NLF_TRY((launch_cols<T, 1, false, true>(p, c, 1, p->batch)));
+    } else {
+        ColsArgs c0{};
+        c0.grid = p->grid_b; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
+        c0.nd = p->n[0]; c0.tw = p->tw_big[0];
+        NLF_TRY((launch_cols<T, 1, false, true>(p, c0, 1, p->batch)));
+        ColsArgs c{};
+        c.grid = p->grid_b; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
+        c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
+        c.nd = p->n[1]; c.tw = p->tw_big[1];
+        NLF_TRY((launch_cols<T, 1, false, true>(p, c, p->n[0], p->batch)));
+    }
+    RowsArgs r{};
+    r.grid = p->grid_b;
+    r.gstride = p->G;
+    r.u = u;
+    r.rstride = p->N;
+    r.n = p->Mr[d - 1];
+    r.dim = d;
+    for (int i = 0; i < 3; ++i) { r.nd[i] = p->n[i]; r.Mr[i] = p->Mr[i]; }
+    r.dec0 = p->dec[0];
+    r.dec1 = p->dec[1];
+    r.dec2 = p->dec[2];
+    r.tw = p->tw_big[d - 1];
+    r.post = p->post;
+    r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
+    r.add_u1 = add_u1 ? 1 : 0;
+    r.mom = p->mom;
+    r.sigma = p->sigma;
+    r.L0 = p->L[0];
+    r.L1 = p->L[1];
+    r.h0 = p->h[0];
+    r.h1 = p->h[1];
+    return launch_rows<T, 1, LOAD_GRID, STORE_U>(p, r, p->batch);
+}
+
+int fft_type2_forward(nlf_plan* p, const void* rho) {
+    return p->prec == NLF_F64 ? type2_forward_t<double>(p, rho) : type2_forward_t<float>(p, rho);
+}
+
+int fft_type1_inverse(nlf_plan* p, void* u, bool add_u1) {
+    return p->prec == NLF_F64 ? type1_inverse_t<double>(p, u, add_u1) : type1_inverse_t<float>(p, u, add_u1);
+}
+
+// Full complex FFT of [batch][n] fields on the plan's (non-oversampled) grid, in place.
+template <typename T, int DIR>
+static int full_t(nlf_plan* p, void* data, int batch) {
+    const int d = p->dim;
+    RowsArgs r{};
+    r.grid = data;
+    r.gstride = p->N;
+    r.n = p->n[d - 1];
+    r.dim = d;
+    r.tw = p->tw_small[d - 1];
+    r.nlines = (int)(p->N / p->n[d - 1]);
+    NLF_TRY((launch_rows<T, DIR, LOAD_GRID, STORE_GRID>(p, r, batch)));
+    if (d == 3) {
+        ColsArgs c{};
+        c.grid = data; c.gstride = p->N; c.n = p->n[1]; c.inner = p->n[2]; c.nd = p->n[1];
+        c.tw = p->tw_small[1];
+        NLF_TRY((launch_cols<T, DIR, false, false>(p, c, p->n[0], batch)));
+    }
+    ColsArgs c0{};
+    c0.grid = data; c0.gstride = p->N; c0.n = p->n[0];
+    c0.inner = (d == 2) ? p->n[1] : (long long)p->n[1] * p->n[2];
+    c0.nd = p->n[0];
+    c0.tw = p->tw_small[0];
+    return launch_cols<T, DIR, false, false>(p, c0, 1, batch);
+}
+
+int fft_full(nlf_plan* p, void* data, int dir, int batch) {
+    if (p->prec == NLF_F64) return dir < 0 ? full_t<double, -1>(p, data, batch) : full_t<double, 1>(p, data, batch);
+    return dir < 0 ? full_t<float, -1>(p, data, batch) : full_t<float, 1>(p, data, batch);
+}
+
+int fill_zero(nlf_plan* p, void* ptr, size_t bytes) {
+    long long words = (long long)(bytes / 8);
+    int blocks = (int)std::min<long long>((words + 255) / 256, 8192);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_fill_zero<double>), dim3(blocks), dim3(256), 0, p->stream, (double*)ptr, words);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+}  // namespace nlf

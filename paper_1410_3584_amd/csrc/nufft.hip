@@ -1,0 +1,614 @@
+// NUFFT stages of the potential evaluation on gfx950 (Sec. 2.1, Eq. 'ifft'; Sec. 2.2, Alg. 1).
+//
+// Gaussian gridding with oversampling 2: a node at position s (in oversampled cells) couples to
+// the 2*msp cells l0+p, p = -msp+1..msp, l0 = floor(s), with the separable weight
+// prod_i exp(-alpha (p_i - delta_i)^2), delta_i = s_i - l0_i.  Nodes are pre-sorted into bins
+// (tiles of the oversampled grid) and cut into chunks of <= kChunk nodes; one workgroup handles
+// one chunk, one thread one node.
+//   interpolation (type-2): the chunk's grid window is staged in LDS (a whole 2D window, or in 3D
+//     one axis-0 plane at a time), each thread gathers its stencil from LDS; the epilogue applies
+//     the kernel symbol and quadrature weight in FP64 (the symbol_weight step, fused).
+//   spreading (type-1): each thread adds its stencil into the LDS window with LDS atomics; the
+//     window is then added to the global grid with one global atomic per window cell.
+// Only half of the node set is evaluated: rho is real, so rhohat(-k) = conj(rhohat(k)), and the
+// node set is symmetric under k -> -k (even n_phi, symmetric Gauss-Legendre in cos theta).
+#include <algorithm>
+#include <cmath>
+
+#include "nlf_internal.h"
+
+namespace nlf {
+
+template <typename T> __device__ __forceinline__ V2<T> mk2(T x, T y);
+template <> __device__ __forceinline__ float2 mk2<float>(float x, float y) { return make_float2(x, y); }
+template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) { return make_double2(x, y); }
+
+__device__ __forceinline__ int wrap(int v, int M) {
+    v %= M;
+    return v < 0 ? v + M : v;
+}
+
+// Separable Gaussian weights for one axis: w[q] = exp(-alpha (q - msp + 1 - delta)^2), computed as
+// exp(-alpha delta^2) * exp(2 alpha delta)^p * exp(-alpha p^2) (Greengard-Lee fast gridding).
+template <typename T, int MSP>
+__device__ __forceinline__ void gauss_weights(double s, const GaussConst& gc, T (&w)[2 * MSP], int& l0) {
+    double f = floor(s);
+    l0 = (int)f;
+    double d = s - f;
+    double e1 = exp(-gc.alpha * d * d);
+    double e2 = exp(2.0 * gc.alpha * d);
+    double e2i = 1.0 / e2;
+    double pw = e1;
+    w[MSP - 1] = (T)(pw * gc.e3[MSP - 1]);
+#pragma unroll
+    for (int q = MSP; q < 2 * MSP; ++q) {
+        pw *= e2;
+        w[q] = (T)(pw * gc.e3[q]);
+    }
+    pw = e1;
+#pragma unroll
+    for (int q = MSP - 2; q >= 0; --q) {
+        pw *= e2i;
+        w[q] = (T)(pw * gc.e3[q]);
+    }
+}
+
+// weight of plane offset a (0..2msp-1) along axis 0, for the 3D plane-streamed kernels
+__device__ __forceinline__ double gauss1(double d, int a, int msp, double alpha) {
+    double x = (double)(a - msp + 1) - d;
+    return exp(-alpha * x * x);
+}
+
+enum { MODE_COULOMB = 0, MODE_LAPLACE = 1, MODE_TYPE2 = 2 };
+
+struct NodeArgs {
+    int dim;
+    int Mr[3], tile[3], W[3];
+    const double* s[3];
+    const Chunk* chunks;
+    int nchunks;
+    GaussConst gc;
+};
+
+struct EpiArgs {
+    int mode;
+    void* out;              // MODE_COULOMB/LAPLACE: cbuf [batch][Mh] sorted; MODE_TYPE2: [batch][M] canonical
+    long long ostride;
+    const double* wfac;
+    const double* gk;
+    const double* mom;      // [batch][4]: m0, m1x, m1y
+    double st2;             // raw sum -> rhohat
+    double kscale[3];       // k_i = s_i * kscale_i
+    const int* perm;
+    int hphi, n_phi, n_theta;
+};
+
+// chunk index of this workgroup: hardware workgroup ids go round-robin over the 8 XCDs; give each
+// XCD a contiguous range of chunks so that chunks of one bin and its neighbours share its L2
+__device__ __forceinline__ int chunk_id(int nchunks) {
+    int b = blockIdx.x;
+    int per = (nchunks + 7) >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ void epilogue(const EpiArgs& e, int batch, int node, double fx, double fy,
+                                         double s0, double s1) {
+    if (e.mode == MODE_TYPE2) {
+        double rx = e.st2 * fx, ry = e.st2 * fy;
+        int hm = e.perm[node];
+        int ab = hm / e.hphi, c = hm - ab * e.hphi;
+        long long m = (long long)ab * e.n_phi + c;
+        long long mp;
+        if (e.n_theta == 1) {
+            mp = m + e.hphi;
+        } else {
+            int a = ab / e.n_theta, bb = ab - a * e.n_theta;
+            mp = ((long long)a * e.n_theta + (e.n_theta - 1 - bb)) * e.n_phi + c + e.hphi;
+        }
+        V2<T>* o = reinterpret_cast<V2<T>*>(e.out) + (long long)batch * e.ostride;
+        o[m] = mk2<T>((T)rx, (T)ry);
+        o[mp] = mk2<T>((T)rx, (T)(-ry));
+        return;
+    }
+    const double w = e.wfac[node];
+    double cx, cy;
+    if (e.mode == MODE_COULOMB) {
+        // c = 2 (2pi)^-d w_m rhohat_m, the Jacobian cancels the Coulomb symbol (Eq. 'ifft')
+        cx = w * fx;
+        cy = w * fy;
+    } else {
+        // c = 2 (2pi)^-2 w_m W(k_m),
+        // W(k) = [rhohat(k) - (m0 - i k.m1) exp(-sigma^2 |k|^2 / 2)] / |k|   (Eq. 'phi2fourier')
+        const double* mo = e.mom + 4 * batch;
+        const double rx = e.st2 * fx, ry = e.st2 * fy;
+        const double g = e.gk[node];
+        const double km1 = s0 * e.kscale[0] * mo[1] + s1 * e.kscale[1] * mo[2];
+        cx = w * (rx - g * mo[0]);
+        cy = w * (ry + g * km1);
+    }
+    V2<T>* o = reinterpret_cast<V2<T>*>(e.out) + (long long)batch * e.ostride;
+    o[node] = mk2<T>((T)cx, (T)cy);
+}
+
+// ---- interpolation ----------------------------------------------------------------------------
+template <typename T, int MSP>
+__global__ void __launch_bounds__(kChunk) k_interp2(const V2<T>* __restrict__ grid, long long gstride,
+                                                    NodeArgs na, EpiArgs ea) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* win = reinterpret_cast<V2<T>*>(smem_raw);
+    const int cid = chunk_id(na.nchunks);
+    if (cid >= na.nchunks) return;
+    const Chunk ch = na.chunks[cid];
+    const int b = blockIdx.y;
+    const V2<T>* g = grid + (long long)b * gstride;
+    const int W0 = na.W[0], W1 = na.W[1];
+    const int o0 = ch.t0 * na.tile[0] - MSP + 1, o1 = ch.t1 * na.tile[1] - MSP + 1;
+    for (int idx = threadIdx.x; idx < W0 * W1; idx += kChunk) {
+        int r = idx / W1, c = idx - r * W1;
+        win[idx] = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= ch.count) return;
+    const int node = ch.start + t;
+    const double sv0 = na.s[0][node], sv1 = na.s[1][node];
+    T w0[2 * MSP], w1[2 * MSP];
+    int l0, l1;
+    gauss_weights<T, MSP>(sv0, na.gc, w0, l0);
+    gauss_weights<T, MSP>(sv1, na.gc, w1, l1);
+    const int r0 = wrap(l0, na.Mr[0]) - ch.t0 * na.tile[0];
+    const int r1 = wrap(l1, na.Mr[1]) - ch.t1 * na.tile[1];
+    T ax = 0, ay = 0;
+    const V2<T>* base = win + r0 * W1 + r1;
+#pragma unroll
+    for (int i = 0; i < 2 * MSP; ++i) {
+        T rx = 0, ry = 0;
+        const V2<T>* row = base + i * W1;
+#pragma unroll
+        for (int j = 0; j < 2 * MSP; ++j) {
+            V2<T> v = row[j];
+            rx += v.x * w1[j];
+            ry += v.y * w1[j];
+        }
+        ax += w0[i] * rx;
+        ay += w0[i] * ry;
+    }
+    epilogue<T>(ea, b, node, (double)ax, (double)ay, sv0, sv1);
+}
+
+template <typename T, int MSP>
+__global__ void __launch_bounds__(kChunk) k_interp3(const V2<T>* __restrict__ grid, long long gstride,
+                                                    NodeArgs na, EpiArgs ea) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* win = reinterpret_cast<V2<T>*>(smem_raw);
+    const int cid = chunk_id(na.nchunks);
+    if (cid >= na.nchunks) return;
+    const Chunk ch = na.chunks[cid];
+    const int b = blockIdx.y;
+    const V2<T>* g = grid + (long long)b * gstride;
+    const int W1 = na.W[1], W2 = na.W[2];
+    const int NP = na.tile[0] + 2 * MSP - 1;
+    const int o0 = ch.t0 * na.tile[0] - MSP + 1;
+    const int o1 = ch.t1 * na.tile[1] - MSP + 1, o2 = ch.t2 * na.tile[2] - MSP + 1;
+    const long long plane = (long long)na.Mr[1] * na.Mr[2];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int node = ch.start + (active ? t : 0);
+    T w1[2 * MSP], w2[2 * MSP];
+    int l0 = 0, l1 = 0, l2 = 0;
+    double d0 = 0;
+    double sv0 = 0, sv1 = 0, sv2 = 0;
+    int r0 = 0, r1 = 0, r2 = 0;
+    if (active) {
+        sv0 = na.s[0][node];
+        sv1 = na.s[1][node];
+        sv2 = na.s[2][node];
+        double f0 = floor(sv0);
+        l0 = (int)f0;
+        d0 = sv0 - f0;
+        gauss_weights<T, MSP>(sv1, na.gc, w1, l1);
+        gauss_weights<T, MSP>(sv2, na.gc, w2, l2);
+        r0 = wrap(l0, na.Mr[0]) - ch.t0 * na.tile[0];
+        r1 = wrap(l1, na.Mr[1]) - ch.t1 * na.tile[1];
+        r2 = wrap(l2, na.Mr[2]) - ch.t2 * na.tile[2];
+    }
+    double ax = 0, ay = 0;
+    for (int q = 0; q < NP; ++q) {
+        const V2<T>* gp = g + (long long)wrap(o0 + q, na.Mr[0]) * plane;
+        for (int idx = threadIdx.x; idx < W1 * W2; idx += kChunk) {
+            int r = idx / W2, c = idx - r * W2;
+            win[idx] = gp[(long long)wrap(o1 + r, na.Mr[1]) * na.Mr[2] + wrap(o2 + c, na.Mr[2])];
+        }
+        __syncthreads();
+        const int a = q - r0;
+        if (active && a >= 0 && a < 2 * MSP) {
+            T px = 0, py = 0;
+            const V2<T>* base = win + r1 * W2 + r2;
+#pragma unroll
+            for (int i = 0; i < 2 * MSP; ++i) {
+                T rx = 0, ry = 0;
+                const V2<T>* row = base + i * W2;
+#pragma unroll
+                for (int j = 0; j < 2 * MSP; ++j) {
+                    V2<T> v = row[j];
+                    rx += v.x * w2[j];
+                    ry += v.y * w2[j];
+                }
+                px += w1[i] * rx;
+                py += w1[i] * ry;
+            }
+            double g0 = gauss1(d0, a, MSP, na.gc.alpha);
+            ax += g0 * (double)px;
+            ay += g0 * (double)py;
+        }
+        __syncthreads();
+    }
+    if (active) epilogue<T>(ea, b, node, ax, ay, sv0, sv1);
+}
+
+// ---- spreading ------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void global_add(T* p, T v) {
+    unsafeAtomicAdd(p, v);
+}
+
+template <typename T, int MSP>
+__global__ void __launch_bounds__(kChunk) k_spread2(V2<T>* __restrict__ grid, long long gstride,
+                                                    const V2<T>* __restrict__ cbuf, long long cstride,
+                                                    NodeArgs na) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* win = reinterpret_cast<V2<T>*>(smem_raw);
+    const int cid = chunk_id(na.nchunks);
+    if (cid >= na.nchunks) return;
+    const Chunk ch = na.chunks[cid];
+    const int b = blockIdx.y;
+    V2<T>* g = grid + (long long)b * gstride;
+    const int W0 = na.W[0], W1 = na.W[1];
+    const int o0 = ch.t0 * na.tile[0] - MSP + 1, o1 = ch.t1 * na.tile[1] - MSP + 1;
+    for (int idx = threadIdx.x; idx < W0 * W1; idx += kChunk) win[idx] = mk2<T>(0, 0);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < ch.count) {
+        const int node = ch.start + t;
+        T w0[2 * MSP], w1[2 * MSP];
+        int l0, l1;
+        gauss_weights<T, MSP>(na.s[0][node], na.gc, w0, l0);
+        gauss_weights<T, MSP>(na.s[1][node], na.gc, w1, l1);
+        const int r0 = wrap(l0, na.Mr[0]) - ch.t0 * na.tile[0];
+        const int r1 = wrap(l1, na.Mr[1]) - ch.t1 * na.tile[1];
+        const V2<T> c = cbuf[(long long)b * cstride + node];
+        V2<T>* base = win + r0 * W1 + r1;
+#pragma unroll
+        for (int i = 0; i < 2 * MSP; ++i) {
+            const T cx = c.x * w0[i], cy = c.y * w0[i];
+            T* row = reinterpret_cast<T*>(base + i * W1);
+#pragma unroll
+            for (int j = 0; j < 2 * MSP; ++j) {
+                lds_add<T>(row + 2 * j, cx * w1[j]);
+                lds_add<T>(row + 2 * j + 1, cy * w1[j]);
+            }
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < W0 * W1; idx += kChunk) {
+        int r = idx / W1, c = idx - r * W1;
+        V2<T> v = win[idx];
+        if (v.x != (T)0 || v.y != (T)0) {
+            T* dst = reinterpret_cast<T*>(g + (long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1]));
+            global_add<T>(dst, v.x);
+            global_add<T>(dst + 1, v.y);
+        }
+    }
+}
+
+template <typename T, int MSP>
+__global__ void __launch_bounds__(kChunk) k_spread3(V2<T>* __restrict__ grid, long long gstride,
+                                                    const V2<T>* __restrict__ cbuf, long long cstride,
+                                                    NodeArgs na) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* win = reinterpret_cast<V2<T>*>(smem_raw);
+    const int cid = chunk_id(na.nchunks);
+    if (cid >= na.nchunks) return;
+    const Chunk ch = na.chunks[cid];
+    const int b = blockIdx.y;
+    V2<T>* g = grid + (long long)b * gstride;
+    const int W1 = na.W[1], W2 = na.W[2];
+    const int NP = na.tile[0] + 2 * MSP - 1;
+    const int o0 = ch.t0 * na.tile[0] - MSP + 1;
+    const int o1 = ch.t1 * na.tile[1] - MSP + 1, o2 = ch.t2 * na.tile[2] - MSP + 1;
+    const long long plane = (long long)na.Mr[1] * na.Mr[2];
+    const int t = threadIdx.x;
+    const bool active = t < ch.count;
+    const int node = ch.start + (active ? t : 0);
+    T w1[2 * MSP], w2[2 * MSP];
+    int l0 = 0, l1 = 0, l2 = 0;
+    double d0 = 0;
+    int r0 = 0, r1 = 0, r2 = 0;
+    V2<T> c = mk2<T>(0, 0);
+    if (active) {
+        double sv0 = na.s[0][node];
+        double f0 = floor(sv0);
+        l0 = (int)f0;
+        d0 = sv0 - f0;
+        gauss_weights<T, MSP>(na.s[1][node], na.gc, w1, l1);
+        gauss_weights<T, MSP>(na.s[2][node], na.gc, w2, l2);
+        r0 = wrap(l0, na.Mr[0]) - ch.t0 * na.tile[0];
+        r1 = wrap(l1, na.Mr[1]) - ch.t1 * na.tile[1];
+        r2 = wrap(l2, na.Mr[2]) - ch.t2 * na.tile[2];
+        c = cbuf[(long long)b * cstride + node];
+    }
+    for (int idx = threadIdx.x; idx < W1 * W2; idx += kChunk) win[idx] = mk2<T>(0, 0);
+    __syncthreads();
+    for (int q = 0; q < NP; ++q) {
+        const int a = q - r0;
+        if (active && a >= 0 && a < 2 * MSP) {
+            const T g0 = (T)gauss1(d0, a, MSP, na.gc.alpha);
+            V2<T>* base = win + r1 * W2 + r2;
+#pragma unroll
+            for (int i = 0; i < 2 * MSP; ++i) {
+                const T f = g0 * w1[i];
+                const T cx = c.x * f, cy = c.y * f;
+                T* row = reinterpret_cast<T*>(base + i * W2);
+#pragma unroll
+                for (int j = 0; j < 2 * MSP; ++j) {
+                    lds_add<T>(row + 2 * j, cx * w2[j]);
+                    lds_add<T>(row + 2 * j + 1, cy * w2[j]);
+                }
+            }
+        }
+        __syncthreads();
+        V2<T>* gp = g + (long long)wrap(o0 + q, na.Mr[0]) * plane;
+        for (int idx = threadIdx.x; idx < W1 * W2; idx += kChunk) {
+            int r = idx / W2, cc = idx - r * W2;
+            V2<T> v = win[idx];
+            if (v.x != (T)0 || v.y != (T)0) {
+                T* dst = reinterpret_cast<T*>(gp + (long long)wrap(o1 + r, na.Mr[1]) * na.Mr[2] + wrap(o2 + cc, na.Mr[2]));
+                global_add<T>(dst, v.x);
+                global_add<T>(dst + 1, v.y);
+                win[idx] = mk2<T>(0, 0);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- fold of a caller-supplied full node vector (type-1 stage entry) ---------------------------
+// Re sum_all c_m e^{ikx} = Re sum_half (c_m + conj(c_{-m})) e^{ikx}
+template <typename T>
+__global__ void k_fold(const V2<T>* __restrict__ c, long long cstride, V2<T>* __restrict__ cbuf, long long Mh,
+                       const int* __restrict__ perm, int hphi, int n_phi, int n_theta) {
+    const int b = blockIdx.y;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < Mh; i += (long long)gridDim.x * blockDim.x) {
+        int hm = perm[i];
+        int ab = hm / hphi, cc = hm - ab * hphi;
+        long long m = (long long)ab * n_phi + cc;
+        long long mp;
+        if (n_theta == 1) mp = m + hphi;
+        else {
+            int a = ab / n_theta, bb = ab - a * n_theta;
+            mp = ((long long)a * n_theta + (n_theta - 1 - bb)) * n_phi + cc + hphi;
+        }
+        V2<T> x = c[(long long)b * cstride + m], y = c[(long long)b * cstride + mp];
+        cbuf[(long long)b * Mh + i] = mk2<T>(x.x + y.x, x.y - y.y);
+    }
+}
+
+// ---- FP64 moments of the density (2D Laplace subtraction, Alg. 1 first step) -------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ rho, long long N, int n1,
+                                                         double L0, double L1, double h0, double h1,
+                                                         double* __restrict__ part) {
+    const int b = blockIdx.y;
+    const T* r = rho + (long long)b * N;
+    double s0 = 0, sx = 0, sy = 0;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long long)gridDim.x * 256) {
+        int j0 = (int)(i / n1), j1 = (int)(i - (long long)j0 * n1);
+        double v = (double)r[i];
+        s0 += v;
+        sx += v * (-L0 + j0 * h0);
+        sy += v * (-L1 + j1 * h1);
+    }
+    __shared__ double sh[3][256];
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = sx;
+    sh[2][threadIdx.x] = sy;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[((long long)b * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_moments_final(const double* __restrict__ part, int nblk, double w, double* __restrict__ mom) {
+    const int b = blockIdx.x;
+    __shared__ double sh[3][256];
+    double a[3] = {0, 0, 0};
+    for (int i = threadIdx.x; i < nblk; i += 256)
+        for (int k = 0; k < 3; ++k) a[k] += part[((long long)b * nblk + i) * 3 + k];
+    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) mom[4 * b + threadIdx.x] = w * sh[threadIdx.x][0];
+    if (threadIdx.x == 3) mom[4 * b + 3] = 0.0;
+}
+
+// ---- host side ---------------------------------------------------------------------------------
+static NodeArgs node_args(const nlf_plan* p) {
+    NodeArgs na{};
+    na.dim = p->dim;
+    for (int i = 0; i < 3; ++i) {
+        na.Mr[i] = p->Mr[i];
+        na.tile[i] = p->tile[i];
+        na.W[i] = p->window[i];
+        na.s[i] = p->s[i];
+    }
+    na.chunks = p->chunks;
+    na.nchunks = p->nchunks;
+    na.gc = p->gc;
+    return na;
+}
+
+static size_t window_bytes(const nlf_plan* p) {
+    size_t e = elem_size(p->prec);
+    return (p->dim == 2) ? (size_t)p->window[0] * p->window[1] * e : (size_t)p->window[1] * p->window[2] * e;
+}
+
+static int grid_chunks(const nlf_plan* p) { return ((p->nchunks + 7) / 8) * 8; }
+
+template <typename T, int MSP>
+static int interp_t(nlf_plan* p, const EpiArgs& ea) {
+    NodeArgs na = node_args(p);
+    dim3 grid(grid_chunks(p), p->batch);
+    const V2<T>* g = reinterpret_cast<const V2<T>*>(p->grid_a);
+    if (p->dim == 2)
+        hipLaunchKernelGGL((k_interp2<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, na, ea);
+    else
+        hipLaunchKernelGGL((k_interp3<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, na, ea);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+template <typename T, int MSP>
+static int spread_t(nlf_plan* p) {
+    NodeArgs na = node_args(p);
+    dim3 grid(grid_chunks(p), p->batch);
+    V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
+    const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
+    if (p->dim == 2)
+        hipLaunchKernelGGL((k_spread2<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, c, p->Mh, na);
+    else
+        hipLaunchKernelGGL((k_spread3<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, c, p->Mh, na);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+// msp dispatch: FP64 plans use msp in [8, 16], FP32 plans msp in [4, 10]
+#define NLF_MSP_CASES_F64(F, T, ...) \
+    case 8: return F<T, 8>(__VA_ARGS__); case 9: return F<T, 9>(__VA_ARGS__); \
+    case 10: return F<T, 10>(__VA_ARGS__); case 11: return F<T, 11>(__VA_ARGS__); \
+    case 12: return F<T, 12>(__VA_ARGS__); case 13: return F<T, 13>(__VA_ARGS__); \
+    case 14: return F<T, 14>(__VA_ARGS__); case 16: return F<T, 16>(__VA_ARGS__);
+#define NLF_MSP_CASES_F32(F, T, ...) \
+    case 4: return F<T, 4>(__VA_ARGS__); case 5: return F<T, 5>(__VA_ARGS__); \
+    case 6: return F<T, 6>(__VA_ARGS__); case 7: return F<T, 7>(__VA_ARGS__); \
+    case 8: return F<T, 8>(__VA_ARGS__); case 9: return F<T, 9>(__VA_ARGS__); \
+    case 10: return F<T, 10>(__VA_ARGS__);
+
+static int bad_msp(const nlf_plan* p) {
+    return set_error(NLF_EUNSUPPORTED, "msp = %d has no compiled kernel for this precision "
+                     "(FP64: 8-14, 16; FP32: 4-10)", p->msp);
+}
+
+static EpiArgs epi_args(const nlf_plan* p, int mode, void* out, long long ostride) {
+    EpiArgs ea{};
+    ea.mode = mode;
+    ea.out = out;
+    ea.ostride = ostride;
+    ea.wfac = p->wfac;
+    ea.gk = p->gk;
+    ea.mom = p->mom;
+    ea.st2 = p->st2;
+    for (int i = 0; i < 3; ++i) ea.kscale[i] = (i < p->dim) ? 3.14159265358979323846 / (2.0 * p->L[i]) : 0.0;
+    ea.perm = p->perm;
+    ea.hphi = p->n_phi / 2;
+    ea.n_phi = p->n_phi;
+    ea.n_theta = p->n_theta;
+    return ea;
+}
+
+int interp(nlf_plan* p, int mode, void* out) {
+    EpiArgs ea;
+    if (mode == MODE_TYPE2) ea = epi_args(p, MODE_TYPE2, out, p->M);
+    else ea = epi_args(p, p->kernel == NLF_LAPLACE2D ? MODE_LAPLACE : MODE_COULOMB, p->cbuf, p->Mh);
+    if (p->prec == NLF_F64) {
+        switch (p->msp) { NLF_MSP_CASES_F64(interp_t, double, p, ea) default: return bad_msp(p); }
+    }
+    switch (p->msp) { NLF_MSP_CASES_F32(interp_t, float, p, ea) default: return bad_msp(p); }
+}
+
+int spread(nlf_plan* p) {
+    NLF_TRY(fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->prec)));
+    if (p->prec == NLF_F64) {
+        switch (p->msp) { NLF_MSP_CASES_F64(spread_t, double, p) default: return bad_msp(p); }
+    }
+    switch (p->msp) { NLF_MSP_CASES_F32(spread_t, float, p) default: return bad_msp(p); }
+}
+
+int fold_c(nlf_plan* p, const void* c) {
+    dim3 grid((unsigned)std::min<long long>((p->Mh + 255) / 256, 4096), p->batch);
+    if (p->prec == NLF_F64)
+        hipLaunchKernelGGL((k_fold<double>), grid, dim3(256), 0, p->stream, (const double2*)c, p->M,
+                           (double2*)p->cbuf, p->Mh, p->perm, p->n_phi / 2, p->n_phi, p->n_theta);
+    else
+        hipLaunchKernelGGL((k_fold<float>), grid, dim3(256), 0, p->stream, (const float2*)c, p->M,
+                           (float2*)p->cbuf, p->Mh, p->perm, p->n_phi / 2, p->n_phi, p->n_theta);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+int moments(nlf_plan* p, const void* rho) {
+    const int nblk = (int)std::min<long long>((p->N + 255) / 256, 1024);
+    dim3 grid(nblk, p->batch);
+    if (p->prec == NLF_F64)
+        hipLaunchKernelGGL((k_moments_partial<double>), grid, dim3(256), 0, p->stream, (const double*)rho, p->N,
+                           p->n[1], p->L[0], p->L[1], p->h[0], p->h[1], p->red);
+    else
+        hipLaunchKernelGGL((k_moments_partial<float>), grid, dim3(256), 0, p->stream, (const float*)rho, p->N,
+                           p->n[1], p->L[0], p->L[1], p->h[0], p->h[1], p->red);
+    NLF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_moments_final, dim3(p->batch), dim3(256), 0, p->stream, p->red, nblk,
+                       p->h[0] * p->h[1], p->mom);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+int potential(nlf_plan* p, const void* rho, void* u) {
+    const bool lap = p->kernel == NLF_LAPLACE2D;
+    if (lap) NLF_TRY(moments(p, rho));
+    NLF_TRY(fft_type2_forward(p, rho));
+    NLF_TRY(interp(p, 0, nullptr));
+    NLF_TRY(spread(p));
+    NLF_TRY(fft_type1_inverse(p, u, lap));
+    return NLF_OK;
+}
+
+}  // namespace nlf
+
+using namespace nlf;
+
+extern "C" {
+
+int nlf_potential(nlf_plan* p, const void* rho, void* u) {
+    clear_error();
+    if (!p || !rho || !u) return set_error(NLF_EINVAL, "plan, rho and u must not be NULL");
+    if (rho == u) return set_error(NLF_EINVAL, "rho and u may not alias");
+    return potential(p, rho, u);
+}
+
+int nlf_type2(nlf_plan* p, const void* rho, void* rhohat) {
+    clear_error();
+    if (!p || !rho || !rhohat) return set_error(NLF_EINVAL, "plan, rho and rhohat must not be NULL");
+    NLF_TRY(fft_type2_forward(p, rho));
+    return interp(p, MODE_TYPE2, rhohat);
+}
+
+int nlf_type1(nlf_plan* p, const void* c, void* u) {
+    clear_error();
+    if (!p || !c || !u) return set_error(NLF_EINVAL, "plan, c and u must not be NULL");
+    NLF_TRY(fold_c(p, c));
+    NLF_TRY(spread(p));
+    return fft_type1_inverse(p, u, false);
+}
+
+}  // extern "C"

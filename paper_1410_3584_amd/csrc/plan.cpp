@@ -1,0 +1,406 @@
+// Plan construction: Fourier-space quadrature nodes (Sec. 2.1, Eq. 'ifft'), Gaussian-gridding
+// parameters of the NUFFT, node binning on the oversampled grid, workspace allocation.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "nlf_internal.h"
+
+namespace nlf {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+void clear_error() { g_err[0] = 0; }
+
+size_t elem_size(int prec) { return prec == NLF_F64 ? 16 : 8; }
+
+int dev_alloc(nlf_plan* p, void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+        return set_error(NLF_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    p->owned.push_back(*ptr);
+    p->workspace_bytes += (long long)bytes;
+    return NLF_OK;
+}
+
+// n-point Gauss-Legendre rule on [-1,1] by Newton's iteration on the three-term recurrence of
+// the Legendre polynomials, in long double; nodes ascending, mirrored so that t[n-1-i] = -t[i]
+// exactly (the node set must be symmetric for the k -> -k pairing of the quadrature nodes).
+static void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w) {
+    t.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        long double x = cosl(pi * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = x; p0 = 1; }
+            dp = n * (x * p1 - p0) / (x * x - 1);
+            long double dx = p1 / dp;
+            x -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        // recompute the derivative at the converged node for the weight
+        long double p0 = 1, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+            long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p1 = x; p0 = 1; }
+        dp = n * (x * p1 - p0) / (x * x - 1);
+        long double wi = 2.0L / ((1 - x * x) * dp * dp);
+        // x is the i-th largest node
+        t[n - 1 - i] = (double)x;
+        t[i] = -(double)x;
+        w[n - 1 - i] = (double)wi;
+        w[i] = (double)wi;
+    }
+    if (n % 2 == 1) t[n / 2] = 0.0;
+}
+
+static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static int upload(nlf_plan* p, void** dst, const void* src, size_t bytes) {
+    NLF_TRY(dev_alloc(p, dst, bytes));
+    NLF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return NLF_OK;
+}
+
+template <typename T>
+static int upload_twiddles(nlf_plan* p, void** dst, int n) {
+    std::vector<T> tw(2 * (size_t)n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int t = 0; t < n; ++t) {
+        long double a = -2.0L * pi * t / n;
+        tw[2 * t] = (T)cosl(a);
+        tw[2 * t + 1] = (T)sinl(a);
+    }
+    return upload(p, dst, tw.data(), tw.size() * sizeof(T));
+}
+
+static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o) {
+    const double pi = 3.14159265358979323846;
+    p->dim = box->dim;
+    p->kernel = kernel;
+    if (p->dim != 2 && p->dim != 3) return set_error(NLF_EUNSUPPORTED, "dim must be 2 or 3 (got %d)", p->dim);
+    if ((kernel == NLF_COULOMB3D && p->dim != 3) ||
+        ((kernel == NLF_COULOMB2D || kernel == NLF_LAPLACE2D) && p->dim != 2))
+        return set_error(NLF_EUNSUPPORTED, "kernel %d does not match dim %d", kernel, p->dim);
+    if (kernel < NLF_COULOMB3D || kernel > NLF_LAPLACE2D)
+        return set_error(NLF_EINVAL, "unknown kernel %d", kernel);
+    p->prec = o ? o->prec : NLF_F64;
+    if (p->prec != NLF_F64 && p->prec != NLF_F32) return set_error(NLF_EINVAL, "prec must be NLF_F64 or NLF_F32");
+    p->batch = (o && o->batch > 0) ? o->batch : 1;
+    p->N = 1;
+    p->G = 1;
+    double hmax = 0;
+    for (int i = 0; i < 3; ++i) {
+        if (i >= p->dim) { p->n[i] = 1; p->Mr[i] = 1; p->L[i] = 0; p->h[i] = 0; continue; }
+        int ni = box->n[i];
+        if (!pow2(ni) || ni < 8 || ni > 1024)
+            return set_error(NLF_EUNSUPPORTED, "n[%d] = %d must be a power of two in [8, 1024]", i, ni);
+        if (!(box->L[i] > 0)) return set_error(NLF_EINVAL, "L[%d] must be positive", i);
+        p->n[i] = ni;
+        p->Mr[i] = 2 * ni;
+        p->L[i] = box->L[i];
+        p->h[i] = 2.0 * box->L[i] / ni;
+        hmax = std::max(hmax, p->h[i]);
+        p->N *= ni;
+        p->G *= 2 * ni;
+    }
+    p->P = (o && o->P > 0) ? o->P : pi / hmax;
+    if (p->P > pi / hmax * (1 + 1e-12))
+        return set_error(NLF_EINVAL, "P = %g exceeds the grid's Nyquist radius pi/max(h) = %g", p->P, pi / hmax);
+    p->n_r = (o && o->n_r > 0) ? o->n_r : p->n[0];
+    p->n_theta = (p->dim == 3) ? ((o && o->n_theta > 0) ? o->n_theta : p->n[0]) : 1;
+    p->n_phi = (o && o->n_phi > 0) ? o->n_phi : 2 * p->n[0];
+    if (p->n_phi % 2) return set_error(NLF_EINVAL, "n_phi must be even (k -> -k pairing)");
+    p->sigma = (o && o->sigma > 0) ? o->sigma : 6.0 * std::sqrt(2.0) / p->P;
+    p->msp = (o && o->msp > 0) ? o->msp : (p->prec == NLF_F64 ? 12 : 7);
+    if (p->msp < 2 || p->msp > kMaxMsp) return set_error(NLF_EINVAL, "msp must be in [2, %d]", kMaxMsp);
+    p->M = (long long)p->n_r * p->n_theta * p->n_phi;
+    p->Mh = p->M / 2;
+
+    // Gaussian gridding with oversampling 2: tau_i = pi msp / (n_i^2 R (R - 1/2)), R = 2.  In units
+    // of oversampled cells the spreading Gaussian is exp(-alpha (p - delta)^2), alpha = 3 pi / (4 msp),
+    // independent of n_i.
+    p->gc.alpha = 3.0 * pi / (4.0 * p->msp);
+    for (int q = 0; q < 2 * kMaxMsp; ++q) {
+        int pp = q - p->msp + 1;
+        p->gc.e3[q] = (q < 2 * p->msp) ? std::exp(-p->gc.alpha * pp * pp) : 0.0;
+    }
+    p->st2 = 1.0;
+    p->post = 1.0;
+    for (int i = 0; i < p->dim; ++i) {
+        p->st2 *= p->h[i] / p->Mr[i];
+        p->post /= p->Mr[i];
+    }
+
+    // tiles
+    for (int i = 0; i < 3; ++i) {
+        int t = (p->dim == 2) ? 16 : 8;
+        if (i >= p->dim) t = 1;
+        p->tile[i] = std::min(t, p->Mr[i]);
+        p->window[i] = (i < p->dim) ? p->tile[i] + 2 * p->msp - 1 : 1;
+    }
+
+    // ---- quadrature nodes (canonical order) -----------------------------------------------
+    std::vector<double> tr, wr, mu, wmu;
+    gauss_legendre(p->n_r, tr, wr);
+    for (int a = 0; a < p->n_r; ++a) {
+        tr[a] = 0.5 * p->P * (tr[a] + 1.0);
+        wr[a] = 0.5 * p->P * wr[a];
+    }
+    if (p->dim == 3) gauss_legendre(p->n_theta, mu, wmu);
+    else { mu.assign(1, 0.0); wmu.assign(1, 1.0); }
+    std::vector<double> cph(p->n_phi), sph(p->n_phi);
+    const long double lpi = 3.141592653589793238462643383279502884L;
+    for (int c = 0; c < p->n_phi; ++c) {
+        long double a = 2.0L * lpi * c / p->n_phi;
+        cph[c] = (double)cosl(a);
+        sph[c] = (double)sinl(a);
+    }
+    const double wphi = 2.0 * pi / p->n_phi;
+    p->k_host.assign((size_t)p->M * p->dim, 0.0);
+    p->w_host.assign((size_t)p->M, 0.0);
+    for (int a = 0; a < p->n_r; ++a)
+        for (int b = 0; b < p->n_theta; ++b)
+            for (int c = 0; c < p->n_phi; ++c) {
+                size_t m = ((size_t)a * p->n_theta + b) * p->n_phi + c;
+                double r = tr[a];
+                if (p->dim == 2) {
+                    p->k_host[2 * m] = r * cph[c];
+                    p->k_host[2 * m + 1] = r * sph[c];
+                    p->w_host[m] = wr[a] * wphi;
+                } else {
+                    double st = std::sqrt((1.0 - mu[b]) * (1.0 + mu[b]));
+                    p->k_host[3 * m] = r * st * cph[c];
+                    p->k_host[3 * m + 1] = r * st * sph[c];
+                    p->k_host[3 * m + 2] = r * mu[b];
+                    p->w_host[m] = wr[a] * wmu[b] * wphi;
+                }
+            }
+
+    // ---- half node set, binning ----------------------------------------------------------------
+    const int hphi = p->n_phi / 2;
+    const long long Mh = p->Mh;
+    std::vector<double> sh[3];
+    for (int i = 0; i < p->dim; ++i) sh[i].resize(Mh);
+    std::vector<int> bin(Mh);
+    int nb[3];
+    for (int i = 0; i < 3; ++i) nb[i] = (i < p->dim) ? p->Mr[i] / p->tile[i] : 1;
+    const long long nbins = (long long)nb[0] * nb[1] * nb[2];
+    std::vector<int> cnt(nbins + 1, 0);
+    for (long long hm = 0; hm < Mh; ++hm) {
+        long long ab = hm / hphi;
+        int c = (int)(hm % hphi);
+        size_t m = (size_t)ab * p->n_phi + c;
+        int bt[3] = {0, 0, 0};
+        for (int i = 0; i < p->dim; ++i) {
+            double s = 2.0 * p->L[i] * p->k_host[(size_t)p->dim * m + i] / pi;
+            sh[i][hm] = s;
+            long long l0 = (long long)std::floor(s);
+            long long lm = ((l0 % p->Mr[i]) + p->Mr[i]) % p->Mr[i];
+            bt[i] = (int)(lm / p->tile[i]);
+        }
+        int bid = (bt[0] * nb[1] + bt[1]) * nb[2] + bt[2];
+        bin[hm] = bid;
+        cnt[bid + 1]++;
+    }
+    for (long long b = 0; b < nbins; ++b) cnt[b + 1] += cnt[b];
+    std::vector<int> order(Mh);
+    {
+        std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+        for (long long hm = 0; hm < Mh; ++hm) order[pos[bin[hm]]++] = (int)hm;
+    }
+    std::vector<Chunk> chunks;
+    for (long long b = 0; b < nbins; ++b) {
+        int beg = cnt[b], end = cnt[b + 1];
+        int bt2 = (int)(b % nb[2]);
+        int bt1 = (int)((b / nb[2]) % nb[1]);
+        int bt0 = (int)(b / ((long long)nb[2] * nb[1]));
+        for (int s = beg; s < end; s += kChunk) {
+            Chunk ch;
+            ch.start = s;
+            ch.count = std::min(kChunk, end - s);
+            ch.t0 = bt0;
+            ch.t1 = bt1;
+            ch.t2 = bt2;
+            ch.pad = 0;
+            chunks.push_back(ch);
+        }
+    }
+    p->nchunks = (int)chunks.size();
+
+    // sorted per-node data
+    std::vector<double> ss[3], wf(Mh), gk;
+    for (int i = 0; i < p->dim; ++i) ss[i].resize(Mh);
+    if (kernel == NLF_LAPLACE2D) gk.resize(Mh);
+    const double inv2pid = std::pow(2.0 * pi, -p->dim);
+    for (long long j = 0; j < Mh; ++j) {
+        int hm = order[j];
+        long long ab = hm / hphi;
+        int c = hm % hphi;
+        size_t m = (size_t)ab * p->n_phi + c;
+        double kk = 0;
+        for (int i = 0; i < p->dim; ++i) {
+            ss[i][j] = sh[i][hm];
+            double ki = p->k_host[(size_t)p->dim * m + i];
+            kk += ki * ki;
+        }
+        double kmag = std::sqrt(kk);
+        // u = Re sum_half 2 c_m e^{ikx}; c_m = (2pi)^-d w_m S_m (Eq. 'ifft' with the Jacobian
+        // cancelled by the Coulomb symbol; Eq. 'phi2fourier' for the Laplace kernel)
+        if (kernel == NLF_LAPLACE2D) {
+            wf[j] = 2.0 * inv2pid * p->w_host[m] / kmag;
+            gk[j] = std::exp(-0.5 * p->sigma * p->sigma * kk);
+        } else {
+            wf[j] = 2.0 * inv2pid * p->w_host[m] * p->st2;
+        }
+    }
+
+    // ---- device buffers ------------------------------------------------------------------------
+    const size_t es = elem_size(p->prec);
+    NLF_TRY(dev_alloc(p, &p->grid_a, (size_t)p->batch * p->G * es));
+    NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * es));
+    NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * es));
+    NLF_TRY(dev_alloc(p, &p->cbuf, (size_t)p->batch * Mh * es));
+    for (int i = 0; i < p->dim; ++i) NLF_TRY(upload(p, (void**)&p->s[i], ss[i].data(), Mh * sizeof(double)));
+    NLF_TRY(upload(p, (void**)&p->wfac, wf.data(), Mh * sizeof(double)));
+    if (kernel == NLF_LAPLACE2D) NLF_TRY(upload(p, (void**)&p->gk, gk.data(), Mh * sizeof(double)));
+    NLF_TRY(upload(p, (void**)&p->perm, order.data(), Mh * sizeof(int)));
+    NLF_TRY(upload(p, (void**)&p->chunks, chunks.data(), chunks.size() * sizeof(Chunk)));
+    for (int i = 0; i < p->dim; ++i) {
+        // 1 / c_g(j') with c_g(j') = sqrt(tau/pi) exp(-tau j'^2): the Fourier coefficients of the
+        // periodised Gaussian exp(-x^2/(4 tau)), tau = pi msp / (3 n^2)
+        double tau = pi * p->msp / (3.0 * (double)p->n[i] * p->n[i]);
+        std::vector<double> d(p->n[i]);
+        for (int j = 0; j < p->n[i]; ++j) {
+            double jc = j - p->n[i] / 2;
+            d[j] = std::sqrt(pi / tau) * std::exp(tau * jc * jc);
+        }
+        NLF_TRY(upload(p, (void**)&p->dec[i], d.data(), d.size() * sizeof(double)));
+        if (p->prec == NLF_F64) {
+            NLF_TRY(upload_twiddles<double>(p, &p->tw_big[i], p->Mr[i]));
+            NLF_TRY(upload_twiddles<double>(p, &p->tw_small[i], p->n[i]));
+        } else {
+            NLF_TRY(upload_twiddles<float>(p, &p->tw_big[i], p->Mr[i]));
+            NLF_TRY(upload_twiddles<float>(p, &p->tw_small[i], p->n[i]));
+        }
+    }
+    NLF_TRY(dev_alloc(p, (void**)&p->mom, (size_t)p->batch * 4 * sizeof(double)));
+    p->red_bytes = (size_t)p->batch * 1024 * 8 * sizeof(double);
+    NLF_TRY(dev_alloc(p, (void**)&p->red, p->red_bytes));
+    return NLF_OK;
+}
+
+}  // namespace nlf
+
+using namespace nlf;
+
+extern "C" {
+
+int nlf_plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* stream, nlf_plan** out) {
+    clear_error();
+    if (!box || !out) return set_error(NLF_EINVAL, "box and out must not be NULL");
+    *out = nullptr;
+    nlf_plan* p = new (std::nothrow) nlf_plan();
+    if (!p) return set_error(NLF_ENOMEM, "host allocation of the plan failed");
+    p->stream = (hipStream_t)stream;
+    int st;
+    try {
+        st = build(p, box, kernel, opts);
+    } catch (const std::bad_alloc&) {
+        st = set_error(NLF_ENOMEM, "host allocation failed while building the plan");
+    } catch (...) {
+        st = set_error(NLF_EINVAL, "unexpected failure while building the plan");
+    }
+    if (st != NLF_OK) {
+        for (void* q : p->owned) (void)hipFree(q);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return NLF_OK;
+}
+
+int nlf_plan_destroy(nlf_plan* p) {
+    clear_error();
+    if (!p) return NLF_OK;
+    (void)hipStreamSynchronize(p->stream);
+    for (void* q : p->owned) (void)hipFree(q);
+    delete p;
+    return NLF_OK;
+}
+
+int nlf_plan_get_info(const nlf_plan* p, nlf_plan_info* info) {
+    clear_error();
+    if (!p || !info) return set_error(NLF_EINVAL, "plan and info must not be NULL");
+    std::memset(info, 0, sizeof *info);
+    info->dim = p->dim;
+    info->kernel = p->kernel;
+    info->prec = p->prec;
+    info->batch = p->batch;
+    info->msp = p->msp;
+    for (int i = 0; i < 3; ++i) {
+        info->n[i] = p->n[i];
+        info->L[i] = p->L[i];
+        info->h[i] = p->h[i];
+    }
+    info->P = p->P;
+    info->sigma = p->sigma;
+    info->n_grid = p->N;
+    info->n_nodes = p->M;
+    info->n_half = p->Mh;
+    info->workspace_bytes = p->workspace_bytes;
+    return NLF_OK;
+}
+
+int nlf_plan_nodes(const nlf_plan* p, double* k_host, double* w_host) {
+    clear_error();
+    if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (k_host) std::memcpy(k_host, p->k_host.data(), p->k_host.size() * sizeof(double));
+    if (w_host) std::memcpy(w_host, p->w_host.data(), p->w_host.size() * sizeof(double));
+    return NLF_OK;
+}
+
+const char* nlf_last_error(void) { return nlf::g_err; }
+
+const char* nlf_strerror(int s) {
+    switch (s) {
+        case NLF_OK: return "ok";
+        case NLF_EINVAL: return "invalid argument";
+        case NLF_EUNSUPPORTED: return "unsupported configuration";
+        case NLF_ENOMEM: return "out of memory";
+        case NLF_EHIP: return "HIP runtime error";
+        case NLF_ENOCONV: return "iteration cap reached without convergence";
+        case NLF_ENONFINITE: return "non-finite value detected";
+        default: return "unknown status";
+    }
+}
+
+const char* nlf_version(void) { return "nlf 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+"""ctypes binding of libnlf.so (argument marshalling only; every step runs in the HIP kernels).
+
+Names follow include/nlf.h.  Device arrays are torch CUDA (HIP) tensors; the library never
+allocates caller arrays, so the wrappers allocate outputs with torch and pass raw pointers.
+The library is loaded after torch so that both share one HIP runtime.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnlf.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+COULOMB3D, COULOMB2D, LAPLACE2D = 1, 2, 3
+
+EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan_nodes",
+           "nlf_potential", "nlf_type2", "nlf_type1", "nlf_ground_state", "nlf_evolve",
+           "nlf_last_error", "nlf_strerror", "nlf_version"]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("n_r", ctypes.c_int), ("n_theta", ctypes.c_int),
+                ("n_phi", ctypes.c_int), ("P", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("msp", ctypes.c_int), ("batch", ctypes.c_int)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("kernel", ctypes.c_int), ("prec", ctypes.c_int),
+                ("batch", ctypes.c_int), ("msp", ctypes.c_int), ("n", ctypes.c_int * 3),
+                ("L", ctypes.c_double * 3), ("h", ctypes.c_double * 3), ("P", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("n_grid", ctypes.c_longlong),
+                ("n_nodes", ctypes.c_longlong), ("n_half", ctypes.c_longlong),
+                ("workspace_bytes", ctypes.c_longlong)]
+
+
+class Phys(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("gamma", ctypes.c_double * 3), ("V_dev", ctypes.c_void_p)]
+
+
+class GfOpts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("eps0", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int)]
+
+
+class GsStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("cg_iters", ctypes.c_int), ("E", ctypes.c_double),
+                ("mu", ctypes.c_double), ("Ekin", ctypes.c_double), ("Epot", ctypes.c_double),
+                ("Eint", ctypes.c_double), ("residual", ctypes.c_double), ("virial", ctypes.c_double),
+                ("mass", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TsOpts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("nsteps", ctypes.c_int), ("order", ctypes.c_int),
+                ("diag_every", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libnlf.so (once).  Raises RuntimeError if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libnlf.so not found at {path}: build it with "
+                           "`python -m paper_1410_3584_amd.build` (no CPU fallback exists)")
+    import torch  # noqa: F401  -- load torch's HIP runtime first so the library shares it
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    lib.nlf_plan_create.argtypes = [ctypes.POINTER(Box), ip, ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    lib.nlf_plan_destroy.argtypes = [vp]
+    lib.nlf_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.nlf_plan_nodes.argtypes = [vp, dp, dp]
+    lib.nlf_potential.argtypes = [vp, vp, vp]
+    lib.nlf_type2.argtypes = [vp, vp, vp]
+    lib.nlf_type1.argtypes = [vp, vp, vp]
+    lib.nlf_ground_state.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(GfOpts), vp, vp,
+                                     ctypes.POINTER(GsStats)]
+    lib.nlf_evolve.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(TsOpts), vp, dp]
+    for f in ["nlf_last_error", "nlf_strerror", "nlf_version"]:
+        getattr(lib, f).restype = ctypes.c_char_p
+    lib.nlf_strerror.argtypes = [ip]
+    _lib = lib
+    return lib
+
+
+class NlfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"nlf status {status}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status != OK:
+        lib = load()
+        msg = lib.nlf_last_error().decode() or lib.nlf_strerror(status).decode()
+        raise NlfError(status, msg)
+    return status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """A potential plan (nlf_plan_create).  kernel: COULOMB3D / COULOMB2D / LAPLACE2D."""
+
+    def __init__(self, n, L, kernel, prec=F64, n_r=0, n_theta=0, n_phi=0, P=0.0, sigma=0.0,
+                 msp=0, batch=1, stream=None):
+        import torch
+        lib = load()
+        self.torch = torch
+        box = Box()
+        box.dim = len(n)
+        for i in range(len(n)):
+            box.n[i] = int(n[i])
+            box.L[i] = float(L[i])
+        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.nlf_plan_create(ctypes.byref(box), int(kernel), ctypes.byref(opts),
+                                   ctypes.c_void_p(stream), ctypes.byref(h)))
+        self._h = h
+        info = PlanInfo()
+        _check(lib.nlf_plan_get_info(h, ctypes.byref(info)))
+        self.info = info
+        self.dim = info.dim
+        self.n = tuple(info.n[i] for i in range(self.dim))
+        self.L = tuple(info.L[i] for i in range(self.dim))
+        self.batch = info.batch
+        self.prec = info.prec
+        self.kernel = kernel
+        self.M = info.n_nodes
+        self.rdtype = torch.float64 if prec == F64 else torch.float32
+        self.cdtype = torch.complex128 if prec == F64 else torch.complex64
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().nlf_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nodes(self):
+        """(k, w) of the full node set in canonical order, as numpy arrays."""
+        k = np.zeros((self.M, self.dim))
+        w = np.zeros(self.M)
+        _check(load().nlf_plan_nodes(self._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return k, w
+
+    def _shape(self):
+        return (self.batch,) + self.n if self.batch > 1 else self.n
+
+    def _check_in(self, t, dtype, numel):
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"expected a contiguous CUDA tensor of {dtype} with {numel} elements, "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+    def potential(self, rho, out=None):
+        N = int(np.prod(self.n)) * self.batch
+        self._check_in(rho, self.rdtype, N)
+        if out is None:
+            out = self.torch.empty(self._shape(), dtype=self.rdtype, device=rho.device)
+        self._check_in(out, self.rdtype, N)
+        _check(load().nlf_potential(self._h, _ptr(rho), _ptr(out)))
+        return out
+
+    def type2(self, rho, out=None):
+        N = int(np.prod(self.n)) * self.batch
+        self._check_in(rho, self.rdtype, N)
+        if out is None:
+            shape = (self.batch, self.M) if self.batch > 1 else (self.M,)
+            out = self.torch.empty(shape, dtype=self.cdtype, device=rho.device)
+        self._check_in(out, self.cdtype, self.M * self.batch)
+        _check(load().nlf_type2(self._h, _ptr(rho), _ptr(out)))
+        return out
+
+    def type1(self, c, out=None):
+        self._check_in(c, self.cdtype, self.M * self.batch)
+        if out is None:
+            out = self.torch.empty(self._shape(), dtype=self.rdtype, device=c.device)
+        _check(load().nlf_type1(self._h, _ptr(c), _ptr(out)))
+        return out
+
+    def ground_state(self, beta, gamma, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
+                     cg_tol=0.0, cg_max_iter=0, psi0=None, V=None, out=None):
+        """nlf_ground_state; returns (psi, [stats dict per field], status)."""
+        phys = Phys()
+        phys.beta = float(beta)
+        for i, g in enumerate(gamma):
+            phys.gamma[i] = float(g)
+        phys.V_dev = V.data_ptr() if V is not None else None
+        gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter)
+        N = int(np.prod(self.n)) * self.batch
+        if psi0 is not None:
+            self._check_in(psi0, self.rdtype, N)
+        if out is None:
+            out = self.torch.empty(self._shape(), dtype=self.rdtype, device="cuda")
+        stats = (GsStats * self.batch)()
+        st = load().nlf_ground_state(self._h, ctypes.byref(phys), ctypes.byref(gf), _ptr(psi0),
+                                     _ptr(out), stats)
+        if st not in (OK, ENOCONV):
+            _check(st)
+        return out, [s.as_dict() for s in stats], st
+
+    def evolve(self, psi, beta, gamma, dt, nsteps, order=2, diag_every=0, V=None):
+        """nlf_evolve in place on psi (complex); returns diagnostics (mass, energy) array or None."""
+        self._check_in(psi, self.cdtype, int(np.prod(self.n)) * self.batch)
+        phys = Phys()
+        phys.beta = float(beta)
+        for i, g in enumerate(gamma):
+            phys.gamma[i] = float(g)
+        phys.V_dev = V.data_ptr() if V is not None else None
+        ts = TsOpts(dt, nsteps, order, diag_every)
+        diag = None
+        dptr = ctypes.POINTER(ctypes.c_double)()
+        if diag_every:
+            diag = np.zeros((nsteps // diag_every + 1, self.batch, 2))
+            dptr = diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(load().nlf_evolve(self._h, ctypes.byref(phys), ctypes.byref(ts), _ptr(psi), dptr))
+        return diag
