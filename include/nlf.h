@@ -121,9 +121,28 @@ int nlf_type2(nlf_plan* plan, const void* rho_dev, void* rhohat_dev);
  * c_dev: [batch][M] complex; u_dev: [batch][n] real; plan precision.                     */
 int nlf_type1(nlf_plan* plan, const void* c_dev, void* u_dev);
 
+/* ---- stage timing (tracing) ----------------------------------------------------------------
+ * When profiling is on, every potential evaluation of the plan records HIP events around each
+ * stage on the plan's stream (this adds an event record between kernels; leave it off for
+ * production use).  nlf_plan_stage_times synchronises the stream, returns the accumulated
+ * milliseconds and the number of timed launches of each stage since the last reset, and resets
+ * the accumulators if `reset` is non-zero.  ms and counts are host arrays of NLF_NSTAGES entries
+ * (either may be NULL).                                                                         */
+#define NLF_STAGE_MOMENTS   0   /* FP64 moments of rho (Laplace kernel only)                       */
+#define NLF_STAGE_FFT_FWD   1   /* precorrect + pad + forward FFT of the oversampled grid          */
+#define NLF_STAGE_INTERP    2   /* Gaussian interpolation to the nodes + symbol x weight           */
+#define NLF_STAGE_ZERO      3   /* clearing the spreading grid                                     */
+#define NLF_STAGE_SPREAD    4   /* Gaussian spreading from the nodes                               */
+#define NLF_STAGE_FFT_INV   5   /* inverse FFT + truncate + postcorrect (+ u1)                     */
+#define NLF_NSTAGES         6
+int nlf_plan_set_profiling(nlf_plan* plan, int on);
+int nlf_plan_stage_times(nlf_plan* plan, double* ms, long long* counts, int reset);
+
 /* ---- solvers -------------------------------------------------------------------------- */
-/* Physical parameters: V = (1/2) sum_i gamma_i^2 x_i^2 unless V_dev != NULL, in which case
- * V_dev ([n] real FP64, device) is used.  beta is the interaction constant of Eq. 'sps-eq'. */
+/* Physical parameters of one field: V = (1/2) sum_i gamma_i^2 x_i^2 unless V_dev != NULL, in
+ * which case V_dev ([n] real FP64, device) is used.  beta is the interaction constant of Eq.
+ * 'sps-eq'.  The solvers take a host array of `batch` entries, one per field; the V_dev of the
+ * first entry, if set, applies to every field.                                               */
 typedef struct {
     double      beta;
     double      gamma[3];
@@ -154,6 +173,8 @@ typedef struct {
  * space, potential by this plan (Sec. 3.1, Eqs. 'gf-eq2'-'gffg33').  The linear part is
  * implicit: (1/tau - Delta/2 + V + beta varphi^n) phi1 = phi^n / tau, solved by conjugate
  * gradients preconditioned with the inverse of (1/tau + alpha + |mu|^2/2) in Fourier space.
+ * phys: host array of `batch` entries.  Converged fields are retired (their kernels exit early)
+ * while the others continue.
  * psi0_dev: [batch][n] real initial guess or NULL (harmonic-oscillator Gaussian);
  * psi_dev: [batch][n] real output; stats: host array of `batch` entries.
  * Returns NLF_ENOCONV if any field hit max_iter (stats still filled).                       */
@@ -162,6 +183,7 @@ int nlf_ground_state(nlf_plan* plan, const nlf_phys* phys, const nlf_gf_opts* gf
 
 /* Time-splitting pseudospectral dynamics (Sec. 4.1, Eqs. 'sps-eq65'-'sps-eq68').
  * order 2: Strang K(dt/2) P(dt) K(dt/2); order 4: Yoshida composition of three Strang steps.
+ * phys: host array of `batch` entries.  Adjacent kinetic half steps are merged.
  * psi_dev: [batch][n] complex, in/out.  diag_host: if non-NULL, receives (mass, energy) per
  * field every diag_every steps and at step 0: 2 * batch * (nsteps/diag_every + 1) doubles.   */
 typedef struct {

@@ -152,39 +152,11 @@ struct RowsArgs {
     // 2D Laplace: u += m0 u11 - m1 . u12 (Sec. 2.2, Eqs. 'phi1_exct', 'phi12_ext')
     int add_u1;
     const double* mom;     // [batch][4]: m0, m1x, m1y
+    const double* u11;     // [N]: u_{1,1} on the grid
     double sigma, L0, L1, h0, h1;
 };
 
-// E1(z) + ln z for z >= 0: the series -gamma - sum_{n>=1} (-z)^n/(n n!) below 1 (Abramowitz &
-// Stegun 5.1.11) and the continued fraction of E1 above (A&S 5.1.22, evaluated by the modified
-// Lentz method).  Smooth at z = 0 where it equals -gamma.
-__device__ double e1_plus_log(double z) {
-    const double egamma = 0.57721566490153286061;
-    if (z < 1.0) {
-        double term = 1.0, sum = 0.0;
-        for (int k = 1; k < 40; ++k) {
-            term *= -z / k;
-            double t = term / k;
-            sum += t;
-            if (fabs(t) < 1e-18 * fabs(sum) + 1e-300) break;
-        }
-        return -egamma - sum;
-    }
-    const double tiny = 1e-300;
-    double b = z + 1.0, c = 1.0 / tiny, d = 1.0 / b, hh = d;
-    for (int i = 1; i < 200; ++i) {
-        double an = -(double)i * i;
-        b += 2.0;
-        d = 1.0 / (an * d + b);
-        c = b + an / c;
-        double del = c * d;
-        hh *= del;
-        if (fabs(del - 1.0) < 1e-17) break;
-    }
-    return hh * exp(-z) + log(z);
-}
-
-template <typename T, int DIR, int LOAD, int STORE>
+template <typename T, typename TIO, int DIR, int LOAD, int STORE>
 __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
@@ -217,7 +189,7 @@ __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
 
     // ---- load
     if (LOAD == LOAD_RHO) {
-        const T* rho = reinterpret_cast<const T*>(a.rho) + (long long)b * a.rstride;
+        const TIO* rho = reinterpret_cast<const TIO*>(a.rho) + (long long)b * a.rstride;
         for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
             int l = idx / n, c = idx - l * n;
             double fac = 1;
@@ -254,15 +226,14 @@ __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
             grid[gl * n + c] = buf[l * pitch + c];
         }
     } else {
-        T* u = reinterpret_cast<T*>(a.u) + (long long)b * a.rstride;
+        TIO* u = reinterpret_cast<TIO*>(a.u) + (long long)b * a.rstride;
         double m0 = 0, m1x = 0, m1y = 0;
         if (a.add_u1) {
             m0 = a.mom[4 * b + 0];
             m1x = a.mom[4 * b + 1];
             m1y = a.mom[4 * b + 2];
         }
-        const double inv4pi = 0.07957747154594766788;   // 1/(4 pi)
-        const double ln2s2 = log(2.0 * a.sigma * a.sigma);
+        const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
         for (int idx = threadIdx.x; idx < nl * ndl; idx += NT) {
             int l = idx / ndl, j = idx - l * ndl;
             double fac;
@@ -272,14 +243,13 @@ __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
             double val = (double)buf[l * pitch + c].x * fac * decl[j] * a.post;
             if (a.add_u1) {
                 // 2D only: line = row j0, element j = column index
+                // u_{1,2} = -(x/|x|^2)(1 - e^{-|x|^2/(2 sigma^2)})/(2 pi), 0 at x = 0 (Eq. 'phi12_ext')
                 double x = -a.L0 + j0 * a.h0, y = -a.L1 + j * a.h1;
                 double r2 = x * x + y * y;
-                double z = r2 / (2.0 * a.sigma * a.sigma);
-                double u11 = -inv4pi * (e1_plus_log(z) + ln2s2);
-                double f = (r2 > 0) ? -(-expm1(-z)) / (2.0 * 3.14159265358979323846 * r2) : 0.0;
-                val += m0 * u11 - (m1x * f * x + m1y * f * y);
+                double f = (r2 > 0) ? expm1(-r2 * inv2s2) / (2.0 * 3.14159265358979323846 * r2) : 0.0;
+                val += m0 * a.u11[(long long)j0 * ndl + j] - (m1x * f * x + m1y * f * y);
             }
-            u[(long long)(line0 + l) * ndl + j] = (T)val;
+            u[(long long)(line0 + l) * ndl + j] = (TIO)val;
         }
     }
 }
@@ -342,7 +312,7 @@ static int ilog2(int v) {
     return l;
 }
 
-template <typename T, int DIR, int LOAD, int STORE>
+template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
 static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     constexpr int E = FftCfg<T>::E, NT = FftCfg<T>::NT;
     a.lg = ilog2(a.n);
@@ -352,11 +322,11 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     size_t lds = (size_t)a.lines_per_wg * a.n * sizeof(V2<T>);
     static bool attr_set = false;
     if (!attr_set) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, DIR, LOAD, STORE>,
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_fft_rows<T, DIR, LOAD, STORE>), grid, dim3(NT), lds, p->stream, a);
+    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -419,23 +389,23 @@ static int type2_forward_t(nlf_plan* p, const void* rho) {
     return NLF_OK;
 }
 
-template <typename T>
+template <typename T, typename TU>
 static int type1_inverse_t(nlf_plan* p, void* u, bool add_u1) {
     const int d = p->dim;
     if (d == 2) {
         ColsArgs c{};
         c.grid = p->grid_b; c.gstride = p->G; c.n = p->Mr[0]; c.inner = p->Mr[1];
-        c.nd = p->n[0]; c.tw = p->tw_big[0];
+        c.nd = p->n[0]; c.tw = p->tw_t1[0];
         NLF_TRY((launch_cols<T, 1, false, true>(p, c, 1, p->batch)));
     } else {
         ColsArgs c0{};
         c0.grid = p->grid_b; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
-        c0.nd = p->n[0]; c0.tw = p->tw_big[0];
+        c0.nd = p->n[0]; c0.tw = p->tw_t1[0];
         NLF_TRY((launch_cols<T, 1, false, true>(p, c0, 1, p->batch)));
         ColsArgs c{};
         c.grid = p->grid_b; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
         c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
-        c.nd = p->n[1]; c.tw = p->tw_big[1];
+        c.nd = p->n[1]; c.tw = p->tw_t1[1];
         NLF_TRY((launch_cols<T, 1, false, true>(p, c, p->n[0], p->batch)));
     }
     RowsArgs r{};
@@ -449,17 +419,18 @@ static int type1_inverse_t(nlf_plan* p, void* u, bool add_u1) {
     r.dec0 = p->dec[0];
     r.dec1 = p->dec[1];
     r.dec2 = p->dec[2];
-    r.tw = p->tw_big[d - 1];
+    r.tw = p->tw_t1[d - 1];
     r.post = p->post;
     r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
     r.add_u1 = add_u1 ? 1 : 0;
     r.mom = p->mom;
+    r.u11 = p->u11;
     r.sigma = p->sigma;
     r.L0 = p->L[0];
     r.L1 = p->L[1];
     r.h0 = p->h[0];
     r.h1 = p->h[1];
-    return launch_rows<T, 1, LOAD_GRID, STORE_U>(p, r, p->batch);
+    return launch_rows<T, 1, LOAD_GRID, STORE_U, TU>(p, r, p->batch);
 }
 
 int fft_type2_forward(nlf_plan* p, const void* rho) {
@@ -467,7 +438,9 @@ int fft_type2_forward(nlf_plan* p, const void* rho) {
 }
 
 int fft_type1_inverse(nlf_plan* p, void* u, bool add_u1) {
-    return p->prec == NLF_F64 ? type1_inverse_t<double>(p, u, add_u1) : type1_inverse_t<float>(p, u, add_u1);
+    if (p->prec == NLF_F64) return type1_inverse_t<double, double>(p, u, add_u1);
+    if (p->t1_prec == NLF_F64) return type1_inverse_t<double, float>(p, u, add_u1);
+    return type1_inverse_t<float, float>(p, u, add_u1);
 }
 
 // Full complex FFT of [batch][n] fields on the plan's (non-oversampled) grid, in place.

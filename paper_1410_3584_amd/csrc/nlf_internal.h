@@ -43,6 +43,16 @@ struct Chunk {
 constexpr int kChunk = 128;   // threads per interpolation/spreading workgroup = nodes per chunk
 constexpr int kMaxMsp = 16;
 
+// A gather-spread work item: up to kGChunk candidate nodes of one output tile of the oversampled
+// grid (gather tiles are 8x8 in 2D and 4x4x4 in 3D: 64 cells).
+struct GItem {
+    int g0, g1, g2;    // tile coordinates
+    int count;         // candidates in this item
+    long long start;   // first entry in the candidate list
+};
+constexpr int kGChunk = 256;
+constexpr int kGCells = 64;
+
 // Gaussian-gridding constants handed to the kernels by value.
 struct GaussConst {
     double alpha;               // exponent scale: g(p) = exp(-alpha (p - delta)^2)
@@ -79,14 +89,37 @@ struct nlf_plan {
     int* perm = nullptr;        // sorted node -> canonical half index
     nlf::Chunk* chunks = nullptr;
     int nchunks = 0;
+    // output-driven spreading: per gather tile, the sorted nodes whose stencil overlaps it
+    int gtile[3] = {1, 1, 1};
+    int use_gather = 0;
+    int* gcand = nullptr;
+    nlf::GItem* gitems = nullptr;
+    int ngitems = 0;
     double* dec[3] = {nullptr, nullptr, nullptr};   // 1 / c_g(j - n/2), length n_i
     void* tw_big[3] = {nullptr, nullptr, nullptr};  // twiddles of length Mr_i (plan precision)
     void* tw_small[3] = {nullptr, nullptr, nullptr};// twiddles of length n_i (solver FFTs)
+    // type-1 side (spreading grid + inverse FFT) precision: the plan's, except FP32 3D plans with
+    // output-driven spreading, which keep that side in FP64 (see plan.cpp)
+    int t1_prec = 0;
+    void* tw_t1[3] = {nullptr, nullptr, nullptr};
     double* mom = nullptr;      // [batch][4] moments m0, m1x, m1y (Laplace) ; scratch
+    double* u11 = nullptr;      // Laplace only: u_{1,1}(x_j) on the grid [N], tabulated at plan time
     double* red = nullptr;      // reduction scratch
     size_t red_bytes = 0;
     long long workspace_bytes = 0;
     std::vector<void*> owned;   // every device allocation, freed on destroy
+
+    // solver workspace (allocated by the first solver call; buffers are in `owned`)
+    void* sws = nullptr;
+    void (*sws_free)(void*) = nullptr;
+
+    // stage timing
+    int profiling = 0;
+    std::vector<hipEvent_t> ev_pool;                 // created lazily, reused
+    size_t ev_used = 0;
+    std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_marks;   // (stage, (start ev, stop ev))
+    double stage_ms[NLF_NSTAGES] = {0};
+    long long stage_cnt[NLF_NSTAGES] = {0};
 };
 
 namespace nlf {
@@ -105,4 +138,8 @@ int interp(nlf_plan* p, int mode, void* out);                 // mode: 0 potenti
 int spread(nlf_plan* p);                                      // cbuf -> grid_b
 int fold_c(nlf_plan* p, const void* c);                       // canonical full c -> cbuf (sorted, folded)
 int potential(nlf_plan* p, const void* rho, void* u);
+
+// stage timing: returns an opaque mark index (or -1 when profiling is off)
+int stage_begin(nlf_plan* p);
+int stage_end(nlf_plan* p, int stage, int mark);
 }  // namespace nlf

@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(kChunk) k_interp3(const V2<T>* __restrict__ gr
         __syncthreads();
         const int a = q - r0;
         if (active && a >= 0 && a < 2 * MSP) {
-            T px = 0, py = 0;
+            double px = 0, py = 0;
             const V2<T>* base = win + r1 * W2 + r2;
 #pragma unroll
             for (int i = 0; i < 2 * MSP; ++i) {
@@ -235,12 +235,12 @@ __global__ void __launch_bounds__(kChunk) k_interp3(const V2<T>* __restrict__ gr
                     rx += v.x * w2[j];
                     ry += v.y * w2[j];
                 }
-                px += w1[i] * rx;
-                py += w1[i] * ry;
+                px += (double)w1[i] * (double)rx;
+                py += (double)w1[i] * (double)ry;
             }
             double g0 = gauss1(d0, a, MSP, na.gc.alpha);
-            ax += g0 * (double)px;
-            ay += g0 * (double)py;
+            ax += g0 * px;
+            ay += g0 * py;
         }
         __syncthreads();
     }
@@ -377,6 +377,164 @@ __global__ void __launch_bounds__(kChunk) k_spread3(V2<T>* __restrict__ grid, lo
     }
 }
 
+// ---- output-driven spreading (gather over candidate nodes, no LDS atomics) ----------------------
+// Weights of one node along one axis restricted to the GT cells o..o+GT-1 of a gather tile:
+// w[k] = sum over p == o + k - l0 (mod Mr), p in [-msp+1, msp], of exp(-alpha (p - delta)^2).
+// When Mr >= 2 msp + GT the representative is unique and consecutive, so the Gaussian is stepped
+// by its ratio exp(-alpha (2 (p - delta) + 1)), itself stepped by exp(-2 alpha) (two exps per axis).
+template <int MSP, int GT>
+__device__ __forceinline__ void tile_weights(double s, int o, int Mr, double alpha, double qq, double (&w)[GT]) {
+    const double f = floor(s);
+    const int l0 = (int)f;
+    const double d = s - f;
+    if (Mr >= 2 * MSP + GT) {
+        int p0 = wrap(o - l0 + MSP - 1, Mr) - MSP + 1;
+        int q0 = (p0 > MSP) ? p0 - Mr : p0;
+        int ks = max(0, -MSP + 1 - q0);
+        double x = (double)(q0 + ks) - d;
+        double g = exp(-alpha * x * x);
+        double r = exp(-alpha * (2.0 * x + 1.0));
+#pragma unroll
+        for (int k = 0; k < GT; ++k) {
+            const int pk = q0 + k;
+            w[k] = (k >= ks && pk <= MSP) ? g : 0.0;
+            if (k >= ks) {
+                g *= r;
+                r *= qq;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < GT; ++k) {
+            double acc = 0;
+            for (int pp = wrap(o + k - l0 + MSP - 1, Mr) - MSP + 1; pp <= MSP; pp += Mr) {
+                double x = (double)pp - d;
+                acc += exp(-alpha * x * x);
+            }
+            w[k] = acc;
+        }
+    }
+}
+
+template <typename T, typename TG, int MSP>
+__global__ void __launch_bounds__(kGChunk) k_gspread2(V2<TG>* __restrict__ grid, long long gstride,
+                                                     const V2<T>* __restrict__ cbuf, long long cstride,
+                                                     NodeArgs na, const GItem* __restrict__ items, int nitems,
+                                                     const int* __restrict__ cand, double qq) {
+    constexpr int GT = 8;
+    // staged weights and partial sums are FP64 in both precisions: the FP32 path stores its
+    // grids and node values in FP32 but accumulates each cell's sum in FP64 registers (same issue
+    // rate as non-packed FP32 on gfx950)
+    __shared__ double2 A[kGChunk][GT];
+    __shared__ double Bw[kGChunk][GT];
+    __shared__ double2 part[kGChunk / 64][64];
+    const int iid = chunk_id(nitems);
+    if (iid >= nitems) return;
+    const GItem it = items[iid];
+    const int b = blockIdx.y;
+    const int t = threadIdx.x;
+    const int o0 = it.g0 * GT, o1 = it.g1 * GT;
+    if (t < it.count) {
+        const int node = cand[it.start + t];
+        double w0[GT], w1[GT];
+        tile_weights<MSP, GT>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
+        tile_weights<MSP, GT>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
+        const V2<T> c = cbuf[(long long)b * cstride + node];
+#pragma unroll
+        for (int k = 0; k < GT; ++k) {
+            A[t][k] = make_double2((double)c.x * w0[k], (double)c.y * w0[k]);
+            Bw[t][k] = w1[k];
+        }
+    }
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63;
+    const int ix = lane >> 3, iy = lane & 7;
+    const int m0 = wv * 64, m1 = min(it.count, m0 + 64);
+    double ax = 0, ay = 0;
+    for (int m = m0; m < m1; ++m) {
+        const double2 a = A[m][ix];
+        const double bw = Bw[m][iy];
+        ax += a.x * bw;
+        ay += a.y * bw;
+    }
+    part[wv][lane] = make_double2(ax, ay);
+    __syncthreads();
+    if (t < 64) {
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int q = 0; q < kGChunk / 64; ++q) {
+            sx += part[q][t].x;
+            sy += part[q][t].y;
+        }
+        if (sx != 0.0 || sy != 0.0) {
+            const int cx = o0 + (t >> 3), cy = o1 + (t & 7);
+            TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride + (long long)cx * na.Mr[1] + cy);
+            global_add<TG>(dst, (TG)sx);
+            global_add<TG>(dst + 1, (TG)sy);
+        }
+    }
+}
+
+template <typename T, typename TG, int MSP>
+__global__ void __launch_bounds__(kGChunk) k_gspread3(V2<TG>* __restrict__ grid, long long gstride,
+                                                     const V2<T>* __restrict__ cbuf, long long cstride,
+                                                     NodeArgs na, const GItem* __restrict__ items, int nitems,
+                                                     const int* __restrict__ cand, double qq) {
+    constexpr int GT = 4;
+    __shared__ double2 A[kGChunk][GT];
+    __shared__ double Bw[kGChunk][GT];
+    __shared__ double Cw[kGChunk][GT];
+    __shared__ double2 part[kGChunk / 64][64];
+    const int iid = chunk_id(nitems);
+    if (iid >= nitems) return;
+    const GItem it = items[iid];
+    const int b = blockIdx.y;
+    const int t = threadIdx.x;
+    const int o0 = it.g0 * GT, o1 = it.g1 * GT, o2 = it.g2 * GT;
+    if (t < it.count) {
+        const int node = cand[it.start + t];
+        double w0[GT], w1[GT], w2[GT];
+        tile_weights<MSP, GT>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
+        tile_weights<MSP, GT>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
+        tile_weights<MSP, GT>(na.s[2][node], o2, na.Mr[2], na.gc.alpha, qq, w2);
+        const V2<T> c = cbuf[(long long)b * cstride + node];
+#pragma unroll
+        for (int k = 0; k < GT; ++k) {
+            A[t][k] = make_double2((double)c.x * w0[k], (double)c.y * w0[k]);
+            Bw[t][k] = w1[k];
+            Cw[t][k] = w2[k];
+        }
+    }
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63;
+    const int i0 = lane >> 4, i1 = (lane >> 2) & 3, i2 = lane & 3;
+    const int m0 = wv * 64, m1 = min(it.count, m0 + 64);
+    double ax = 0, ay = 0;
+    for (int m = m0; m < m1; ++m) {
+        const double2 a = A[m][i0];
+        const double bw = Bw[m][i1] * Cw[m][i2];
+        ax += a.x * bw;
+        ay += a.y * bw;
+    }
+    part[wv][lane] = make_double2(ax, ay);
+    __syncthreads();
+    if (t < 64) {
+        double sx = 0, sy = 0;
+#pragma unroll
+        for (int q = 0; q < kGChunk / 64; ++q) {
+            sx += part[q][t].x;
+            sy += part[q][t].y;
+        }
+        if (sx != 0.0 || sy != 0.0) {
+            const int c0 = o0 + (t >> 4), c1 = o1 + ((t >> 2) & 3), c2 = o2 + (t & 3);
+            TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride +
+                                            ((long long)c0 * na.Mr[1] + c1) * na.Mr[2] + c2);
+            global_add<TG>(dst, (TG)sx);
+            global_add<TG>(dst + 1, (TG)sy);
+        }
+    }
+}
+
 // ---- fold of a caller-supplied full node vector (type-1 stage entry) ---------------------------
 // Re sum_all c_m e^{ikx} = Re sum_half (c_m + conj(c_{-m})) e^{ikx}
 template <typename T>
@@ -482,9 +640,26 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea) {
 template <typename T, int MSP>
 static int spread_t(nlf_plan* p) {
     NodeArgs na = node_args(p);
-    dim3 grid(grid_chunks(p), p->batch);
     V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
     const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
+    if (p->use_gather) {
+        dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
+        const double qq = exp(-2.0 * p->gc.alpha);
+        if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid (3D)
+            double2* g64 = reinterpret_cast<double2*>(p->grid_b);
+            hipLaunchKernelGGL((k_gspread3<T, double, MSP>), ggrid, dim3(kGChunk), 0, p->stream, g64, p->G, c, p->Mh,
+                               na, p->gitems, p->ngitems, p->gcand, qq);
+        } else if (p->dim == 2) {
+            hipLaunchKernelGGL((k_gspread2<T, T, MSP>), ggrid, dim3(kGChunk), 0, p->stream, g, p->G, c, p->Mh, na,
+                               p->gitems, p->ngitems, p->gcand, qq);
+        } else {
+            hipLaunchKernelGGL((k_gspread3<T, T, MSP>), ggrid, dim3(kGChunk), 0, p->stream, g, p->G, c, p->Mh, na,
+                               p->gitems, p->ngitems, p->gcand, qq);
+        }
+        NLF_HIP(hipGetLastError());
+        return NLF_OK;
+    }
+    dim3 grid(grid_chunks(p), p->batch);
     if (p->dim == 2)
         hipLaunchKernelGGL((k_spread2<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, c, p->Mh, na);
     else
@@ -537,12 +712,16 @@ int interp(nlf_plan* p, int mode, void* out) {
     switch (p->msp) { NLF_MSP_CASES_F32(interp_t, float, p, ea) default: return bad_msp(p); }
 }
 
-int spread(nlf_plan* p) {
-    NLF_TRY(fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->prec)));
+static int spread_only(nlf_plan* p) {
     if (p->prec == NLF_F64) {
         switch (p->msp) { NLF_MSP_CASES_F64(spread_t, double, p) default: return bad_msp(p); }
     }
     switch (p->msp) { NLF_MSP_CASES_F32(spread_t, float, p) default: return bad_msp(p); }
+}
+
+int spread(nlf_plan* p) {
+    NLF_TRY(fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
+    return spread_only(p);
 }
 
 int fold_c(nlf_plan* p, const void* c) {
@@ -573,13 +752,21 @@ int moments(nlf_plan* p, const void* rho) {
     return NLF_OK;
 }
 
+#define NLF_STAGE(p, id, call)               \
+    do {                                     \
+        int mk_ = stage_begin(p);            \
+        NLF_TRY(call);                       \
+        NLF_TRY(stage_end(p, id, mk_));      \
+    } while (0)
+
 int potential(nlf_plan* p, const void* rho, void* u) {
     const bool lap = p->kernel == NLF_LAPLACE2D;
-    if (lap) NLF_TRY(moments(p, rho));
-    NLF_TRY(fft_type2_forward(p, rho));
-    NLF_TRY(interp(p, 0, nullptr));
-    NLF_TRY(spread(p));
-    NLF_TRY(fft_type1_inverse(p, u, lap));
+    if (lap) NLF_STAGE(p, NLF_STAGE_MOMENTS, moments(p, rho));
+    NLF_STAGE(p, NLF_STAGE_FFT_FWD, fft_type2_forward(p, rho));
+    NLF_STAGE(p, NLF_STAGE_INTERP, interp(p, 0, nullptr));
+    NLF_STAGE(p, NLF_STAGE_ZERO, fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
+    NLF_STAGE(p, NLF_STAGE_SPREAD, spread_only(p));
+    NLF_STAGE(p, NLF_STAGE_FFT_INV, fft_type1_inverse(p, u, lap));
     return NLF_OK;
 }
 

@@ -82,6 +82,36 @@ static void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& w
 
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// E1(z) + ln z for z >= 0 in long double: the power series -gamma - sum_{k>=1} (-z)^k / (k k!)
+// (Abramowitz & Stegun 5.1.11) below z = 1, the continued fraction of E1 (A&S 5.1.22, modified Lentz
+// evaluation) above; E1 is dropped beyond z = 45 where it is below the rounding of ln z.
+static long double e1_plus_log(long double z) {
+    const long double egamma = 0.577215664901532860606512090082402431L;
+    if (z < 1.0L) {
+        long double term = 1.0L, sum = 0.0L;
+        for (int k = 1; k < 60; ++k) {
+            term *= -z / k;
+            long double t = term / k;
+            sum += t;
+            if (fabsl(t) <= 1e-21L * fabsl(sum)) break;
+        }
+        return -egamma - sum;
+    }
+    if (z > 45.0L) return logl(z);
+    const long double tiny = 1e-4000L;
+    long double b = z + 1.0L, c = 1.0L / tiny, d = 1.0L / b, h = d;
+    for (int i = 1; i < 1000; ++i) {
+        long double an = -(long double)i * i;
+        b += 2.0L;
+        d = 1.0L / (an * d + b);
+        c = b + an / c;
+        long double del = c * d;
+        h *= del;
+        if (fabsl(del - 1.0L) < 1e-19L) break;
+    }
+    return h * expl(-z) + logl(z);
+}
+
 static int upload(nlf_plan* p, void** dst, const void* src, size_t bytes) {
     NLF_TRY(dev_alloc(p, dst, bytes));
     NLF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
@@ -254,6 +284,92 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     }
     p->nchunks = (int)chunks.size();
 
+    // ---- candidate lists for the output-driven spreading ------------------------------------
+    // A node at l0 touches cells (l0 + p) mod Mr, p = -msp+1..msp, along each axis; list it under
+    // every gather tile its stencil overlaps.  Plans whose list would exceed kMaxCand entries keep
+    // the scatter kernels.
+    {
+        const long long kMaxCand = 400000000LL;
+        int gt[3], ng[3];
+        for (int i = 0; i < 3; ++i) {
+            gt[i] = (i < p->dim) ? std::min((p->dim == 2 ? 8 : 4), p->Mr[i]) : 1;
+            p->gtile[i] = gt[i];
+            ng[i] = (i < p->dim) ? p->Mr[i] / gt[i] : 1;
+        }
+        const long long ntiles = (long long)ng[0] * ng[1] * ng[2];
+        auto axis_tiles = [&](double s, int i, int* out) -> int {
+            long long l0 = (long long)std::floor(s);
+            int cnt = 0;
+            if (2 * p->msp >= p->Mr[i]) {
+                for (int t = 0; t < ng[i]; ++t) out[cnt++] = t;
+                return cnt;
+            }
+            int first = (int)((((l0 - p->msp + 1) % p->Mr[i]) + p->Mr[i]) % p->Mr[i]) / gt[i];
+            int last = (int)((((l0 + p->msp) % p->Mr[i]) + p->Mr[i]) % p->Mr[i]) / gt[i];
+            int t = first;
+            while (true) {
+                out[cnt++] = t;
+                if (t == last || cnt == ng[i]) break;
+                t = (t + 1) % ng[i];
+            }
+            return cnt;
+        };
+        std::vector<long long> tcount(ntiles + 1, 0);
+        long long total = 0;
+        std::vector<int> tl[3];
+        for (int i = 0; i < 3; ++i) tl[i].resize(std::max(ng[i], 1));
+        for (long long j = 0; j < Mh && total <= kMaxCand; ++j) {
+            int hm = order[j];
+            int c3[3] = {1, 1, 1};
+            for (int i = 0; i < p->dim; ++i) c3[i] = axis_tiles(sh[i][hm], i, tl[i].data());
+            for (int a = 0; a < c3[0]; ++a)
+                for (int b = 0; b < c3[1]; ++b)
+                    for (int c = 0; c < c3[2]; ++c) {
+                        int t0 = p->dim > 0 ? tl[0][a] : 0, t1 = tl[1][b], t2 = p->dim == 3 ? tl[2][c] : 0;
+                        long long tid = ((long long)t0 * ng[1] + t1) * ng[2] + t2;
+                        tcount[tid + 1]++;
+                    }
+            total += (long long)c3[0] * c3[1] * c3[2];
+        }
+        if (total <= kMaxCand) {
+            for (long long t = 0; t < ntiles; ++t) tcount[t + 1] += tcount[t];
+            std::vector<int> cand(total);
+            std::vector<long long> pos(tcount.begin(), tcount.end() - 1);
+            for (long long j = 0; j < Mh; ++j) {
+                int hm = order[j];
+                int c3[3] = {1, 1, 1};
+                for (int i = 0; i < p->dim; ++i) c3[i] = axis_tiles(sh[i][hm], i, tl[i].data());
+                for (int a = 0; a < c3[0]; ++a)
+                    for (int b = 0; b < c3[1]; ++b)
+                        for (int c = 0; c < c3[2]; ++c) {
+                            int t0 = tl[0][a], t1 = tl[1][b], t2 = p->dim == 3 ? tl[2][c] : 0;
+                            long long tid = ((long long)t0 * ng[1] + t1) * ng[2] + t2;
+                            cand[pos[tid]++] = (int)j;
+                        }
+            }
+            std::vector<GItem> items;
+            for (long long t = 0; t < ntiles; ++t) {
+                long long beg = tcount[t], end = tcount[t + 1];
+                int g2 = (int)(t % ng[2]);
+                int g1 = (int)((t / ng[2]) % ng[1]);
+                int g0 = (int)(t / ((long long)ng[2] * ng[1]));
+                for (long long s0 = beg; s0 < end; s0 += kGChunk) {
+                    GItem it;
+                    it.g0 = g0;
+                    it.g1 = g1;
+                    it.g2 = g2;
+                    it.count = (int)std::min<long long>(kGChunk, end - s0);
+                    it.start = s0;
+                    items.push_back(it);
+                }
+            }
+            p->ngitems = (int)items.size();
+            p->use_gather = 1;
+            NLF_TRY(upload(p, (void**)&p->gcand, cand.data(), std::max<size_t>(1, cand.size()) * sizeof(int)));
+            NLF_TRY(upload(p, (void**)&p->gitems, items.data(), std::max<size_t>(1, items.size()) * sizeof(GItem)));
+        }
+    }
+
     // sorted per-node data
     std::vector<double> ss[3], wf(Mh), gk;
     for (int i = 0; i < p->dim; ++i) ss[i].resize(Mh);
@@ -283,9 +399,15 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
 
     // ---- device buffers ------------------------------------------------------------------------
     const size_t es = elem_size(p->prec);
+    // In 3D the type-1 output is divided by the Gaussian's Fourier coefficients, up to ~e^{pi msp/4}
+    // larger at the corners of the box than at its centre; FP32 rounding of the inverse transform is
+    // amplified by that factor.  FP32 3D plans with output-driven spreading therefore keep the
+    // spreading grid and the inverse FFT in FP64 (node values, the type-2 side and the interpolation
+    // stay FP32).
+    p->t1_prec = (p->prec == NLF_F32 && p->dim == 3 && p->use_gather) ? NLF_F64 : p->prec;
     NLF_TRY(dev_alloc(p, &p->grid_a, (size_t)p->batch * p->G * es));
-    NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * es));
-    NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * es));
+    NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
+    NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_TRY(dev_alloc(p, &p->cbuf, (size_t)p->batch * Mh * es));
     for (int i = 0; i < p->dim; ++i) NLF_TRY(upload(p, (void**)&p->s[i], ss[i].data(), Mh * sizeof(double)));
     NLF_TRY(upload(p, (void**)&p->wfac, wf.data(), Mh * sizeof(double)));
@@ -309,10 +431,69 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
             NLF_TRY(upload_twiddles<float>(p, &p->tw_big[i], p->Mr[i]));
             NLF_TRY(upload_twiddles<float>(p, &p->tw_small[i], p->n[i]));
         }
+        if (p->t1_prec == p->prec) p->tw_t1[i] = p->tw_big[i];
+        else NLF_TRY(upload_twiddles<double>(p, &p->tw_t1[i], p->Mr[i]));
     }
     NLF_TRY(dev_alloc(p, (void**)&p->mom, (size_t)p->batch * 4 * sizeof(double)));
+    if (kernel == NLF_LAPLACE2D) {
+        // u_{1,1}(x) = -(E1(|x|^2/(2 sigma^2)) + 2 ln|x|) / (4 pi), (gamma_e - ln 2 sigma^2)/(4 pi) at 0
+        // (Sec. 2.2, Eq. 'phi1_exct'), written as -(E1(z) + ln z + ln 2 sigma^2)/(4 pi), smooth at 0
+        std::vector<double> u(p->N);
+        const long double s2 = (long double)p->sigma * p->sigma;
+        const long double ln2s2 = logl(2.0L * s2);
+        const long double inv4pi = 1.0L / (4.0L * 3.141592653589793238462643383279502884L);
+        for (int j0 = 0; j0 < p->n[0]; ++j0)
+            for (int j1 = 0; j1 < p->n[1]; ++j1) {
+                long double x = -(long double)p->L[0] + j0 * (long double)p->h[0];
+                long double y = -(long double)p->L[1] + j1 * (long double)p->h[1];
+                long double z = (x * x + y * y) / (2.0L * s2);
+                u[(size_t)j0 * p->n[1] + j1] = (double)(-inv4pi * (e1_plus_log(z) + ln2s2));
+            }
+        NLF_TRY(upload(p, (void**)&p->u11, u.data(), u.size() * sizeof(double)));
+    }
     p->red_bytes = (size_t)p->batch * 1024 * 8 * sizeof(double);
     NLF_TRY(dev_alloc(p, (void**)&p->red, p->red_bytes));
+    return NLF_OK;
+}
+
+static int next_event(nlf_plan* p, size_t* idx) {
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e;
+        NLF_HIP(hipEventCreate(&e));
+        p->ev_pool.push_back(e);
+    }
+    *idx = p->ev_used++;
+    return NLF_OK;
+}
+
+int stage_begin(nlf_plan* p) {
+    if (!p->profiling) return -1;
+    size_t i;
+    if (next_event(p, &i) != NLF_OK) return -1;
+    if (hipEventRecord(p->ev_pool[i], p->stream) != hipSuccess) return -1;
+    return (int)i;
+}
+
+int stage_end(nlf_plan* p, int stage, int mark) {
+    if (!p->profiling || mark < 0) return NLF_OK;
+    size_t j;
+    NLF_TRY(next_event(p, &j));
+    NLF_HIP(hipEventRecord(p->ev_pool[j], p->stream));
+    p->ev_marks.push_back({stage, {(size_t)mark, j}});
+    return NLF_OK;
+}
+
+static int drain_events(nlf_plan* p) {
+    if (p->ev_marks.empty()) { p->ev_used = 0; return NLF_OK; }
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    for (auto& m : p->ev_marks) {
+        float ms = 0;
+        NLF_HIP(hipEventElapsedTime(&ms, p->ev_pool[m.second.first], p->ev_pool[m.second.second]));
+        p->stage_ms[m.first] += ms;
+        p->stage_cnt[m.first] += 1;
+    }
+    p->ev_marks.clear();
+    p->ev_used = 0;
     return NLF_OK;
 }
 
@@ -346,10 +527,32 @@ int nlf_plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* 
     return NLF_OK;
 }
 
+int nlf_plan_set_profiling(nlf_plan* p, int on) {
+    clear_error();
+    if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (!on) NLF_TRY(drain_events(p));
+    p->profiling = on ? 1 : 0;
+    return NLF_OK;
+}
+
+int nlf_plan_stage_times(nlf_plan* p, double* ms, long long* counts, int reset) {
+    clear_error();
+    if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    NLF_TRY(drain_events(p));
+    for (int i = 0; i < NLF_NSTAGES; ++i) {
+        if (ms) ms[i] = p->stage_ms[i];
+        if (counts) counts[i] = p->stage_cnt[i];
+        if (reset) { p->stage_ms[i] = 0; p->stage_cnt[i] = 0; }
+    }
+    return NLF_OK;
+}
+
 int nlf_plan_destroy(nlf_plan* p) {
     clear_error();
     if (!p) return NLF_OK;
     (void)hipStreamSynchronize(p->stream);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    if (p->sws && p->sws_free) p->sws_free(p->sws);
     for (void* q : p->owned) (void)hipFree(q);
     delete p;
     return NLF_OK;

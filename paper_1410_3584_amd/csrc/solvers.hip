@@ -1,21 +1,853 @@
-// Ground-state and dynamics solvers (filled in below the potential path).
+// Ground-state and dynamics solvers on gfx950, built on the plan's NUFFT potential.
+//
+// Ground state (Sec. 3.1, Eqs. 'gf-eq2', 'gf-colb2', 'gffg33'): gradient flow with discrete
+// normalization, backward Euler in time, Fourier pseudospectral in space, potential lagged at
+// phi^n.  The backward-Euler step is implicit in the whole linear part,
+//     (1/tau - Delta/2 + W) phi1 = phi^n / tau,   W = V + beta varphi^n,
+// solved by preconditioned conjugate gradients.  The preconditioner is the Fourier multiplier
+// D = 1/(1/tau + a + |mu|^2/2), a = (max W + min W)/2.  The search direction is kept in Fourier
+// space, so one iteration costs two complex FFTs: r -> r^, and (p^ + i K p^) -> (p, K p) with
+// K = |mu|^2/2 (both p and K p are real, so they share one inverse transform).
+// Stopping rule max|phi^{n+1} - phi^n| / tau <= eps0 (Sec. 3.2); energies, chemical potential and
+// virial identity as in Sec. 3.2.  All reductions are FP64.
+//
+// Dynamics (Sec. 4.1, Eqs. 'sps-eq65'-'sps-eq68'): Strang splitting; the kinetic flow is exact
+// in Fourier space, the potential flow psi <- exp(-i (V + beta varphi) dt) psi is exact because
+// |psi| does not change during it.  Order 4 composes three Strang steps (Yoshida).  Phase
+// arguments are formed in FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "nlf_internal.h"
+
+namespace nlf {
+
+constexpr int RB_T = 256;      // threads per block of the pointwise/reduction kernels
+constexpr int MAXBLK = 256;    // reduction partials per field
+
+template <typename T> __device__ __forceinline__ V2<T> mkc(T x, T y);
+template <> __device__ __forceinline__ float2 mkc<float>(float x, float y) { return make_float2(x, y); }
+template <> __device__ __forceinline__ double2 mkc<double>(double x, double y) { return make_double2(x, y); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+// block-wide reductions (blockDim = RB_T); the result is valid in every thread
+__device__ double block_sum(double v) {
+    __shared__ double sh[RB_T / 64];
+    __shared__ double res;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < RB_T / 64; ++i) s += sh[i];
+        res = s;
+    }
+    __syncthreads();
+    double r = res;
+    __syncthreads();
+    return r;
+}
+__device__ double block_max(double v) {
+    __shared__ double sh[RB_T / 64];
+    __shared__ double res;
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = sh[0];
+        for (int i = 1; i < RB_T / 64; ++i) s = fmax(s, sh[i]);
+        res = s;
+    }
+    __syncthreads();
+    double r = res;
+    __syncthreads();
+    return r;
+}
+// sum of the nblk partials of one field (every block recomputes it; nblk <= MAXBLK)
+__device__ double sum_parts(const double* part, int nblk) {
+    double v = (threadIdx.x < nblk) ? part[threadIdx.x] : 0.0;
+    return block_sum(v);
+}
+__device__ double max_parts(const double* part, int nblk) {
+    double v = (threadIdx.x < nblk) ? part[threadIdx.x] : -1e308;
+    return block_max(v);
+}
+// -(min over the partials), computed as a max of negated values
+__device__ double max_parts_neg(const double* part, int nblk) {
+    double v = (threadIdx.x < nblk) ? -part[threadIdx.x] : -1e308;
+    return block_max(v);
+}
+
+// Grid geometry handed to the solver kernels.
+struct Geo {
+    int dim;
+    int n[3];
+    double L[3], h[3];
+    long long N;
+    double dv;        // prod h_i
+};
+
+__device__ __forceinline__ void coords(const Geo& g, long long i, double x[3], int j[3]) {
+    long long r = i;
+    for (int a = g.dim - 1; a >= 0; --a) {
+        j[a] = (int)(r % g.n[a]);
+        r /= g.n[a];
+        x[a] = -g.L[a] + j[a] * g.h[a];
+    }
+}
+// |mu|^2 of the discrete Fourier mode at flat index i (mu_l = pi l / L, l in [-n/2, n/2))
+__device__ __forceinline__ double mu2(const Geo& g, long long i) {
+    long long r = i;
+    double s = 0;
+    for (int a = g.dim - 1; a >= 0; --a) {
+        int l = (int)(r % g.n[a]);
+        r /= g.n[a];
+        if (l >= g.n[a] / 2) l -= g.n[a];
+        double m = 3.14159265358979323846 * l / g.L[a];
+        s += m * m;
+    }
+    return s;
+}
+
+// Per-field parameters and scalars live in device memory: Fld[b].
+struct Fld {
+    double beta, g2[3];          // beta, gamma_i^2
+    double tau;
+    double a;                    // preconditioner shift
+    double rz, rz_old, pAp, rr, bb;
+    double norm2, res;
+    double cgtol;                // inner relative tolerance of the current solve
+    double cgtol_min;            // the caller's (final) inner tolerance
+    int cg_last;                 // iterations of the current solve
+    int pad2;
+    int conv;                    // PCG converged
+    int done;                    // outer flow converged (field retired)
+    int cg_iters;
+    int first;                   // first PCG iteration of the current solve
+    int nonfinite;
+    int pad;
+};
+
+__device__ __forceinline__ double trapV(const Geo& g, const Fld& f, const double* Vext, long long i, const double x[3]) {
+    if (Vext) return Vext[i];
+    double v = 0;
+    for (int a = 0; a < g.dim; ++a) v += f.g2[a] * x[a] * x[a];
+    return 0.5 * v;
+}
+
+// ---- ground-state kernels -------------------------------------------------------------------
+// HO Gaussian initial guess prod (gamma_i/pi)^{1/4} exp(-gamma_i x_i^2 / 2) (Sec. 3.2 "Gaussian")
+template <typename T>
+__global__ void k_ho_init(Geo g, const Fld* fl, T* phi) {
+    const int b = blockIdx.y;
+    const Fld f = fl[b];
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        double x[3];
+        int j[3];
+        coords(g, i, x, j);
+        double v = 1;
+        for (int a = 0; a < g.dim; ++a) {
+            double ga = sqrt(f.g2[a]);
+            v *= pow(ga / 3.14159265358979323846, 0.25) * exp(-0.5 * ga * x[a] * x[a]);
+        }
+        phi[(long long)b * g.N + i] = (T)v;
+    }
+}
+
+// partial sums of h^d sum v^2 (norm2) per field
+template <typename T>
+__global__ void k_norm2_part(Geo g, const Fld* fl, const T* v, double* part) {
+    const int b = blockIdx.y;
+    if (fl[b].done) return;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        double a = (double)v[(long long)b * g.N + i];
+        s += a * a;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[b * MAXBLK + blockIdx.x] = s * g.dv;
+}
+
+// phi <- v / ||v||; optionally residual max|phi_new - phi_old|/tau partials; rho = phi^2
+template <typename T>
+__global__ void k_normalize(Geo g, Fld* fl, const T* v, T* phi, T* rho, const double* part_n, double* part_r,
+                            int nblk, int track_res) {
+    const int b = blockIdx.y;
+    if (fl[b].done) return;
+    const double nrm = sqrt(sum_parts(part_n + b * MAXBLK, nblk));
+    const double inv = 1.0 / nrm;
+    const double tau = fl[b].tau;
+    double m = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double nv = (double)v[k] * inv;
+        if (track_res) m = fmax(m, fabs(nv - (double)phi[k]) / tau);
+        phi[k] = (T)nv;
+        rho[k] = (T)(nv * nv);
+    }
+    if (track_res) {
+        m = block_max(m);
+        if (threadIdx.x == 0) part_r[b * MAXBLK + blockIdx.x] = m;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) fl[b].norm2 = nrm * nrm;
+}
+
+// outer residual max|phi^{n+1} - phi^n| / tau; retire the field at eps0.  The next inner solve
+// only needs to be accurate relative to the size of the step it computes, so its tolerance
+// follows the residual down to the caller's tolerance: max(cg_tol, min(1e-3, 1e-3 tau res)).
+template <typename T>
+__global__ void k_residual_final(Fld* fl, const double* part_r, int nblk, double eps0) {
+    const int b = blockIdx.x;
+    if (fl[b].done) return;
+    double r = max_parts(part_r + b * MAXBLK, nblk);
+    if (threadIdx.x == 0) {
+        fl[b].res = r;
+        if (!(r == r) || r > 1e300) fl[b].nonfinite = 1;
+        if (r <= eps0) fl[b].done = 1;
+        fl[b].cgtol = fmax(fl[b].cgtol_min, fmin(1e-3, 1e-3 * fl[b].tau * r));
+    }
+}
+
+// W = V + beta varphi; partial max/min of W for the preconditioner shift; cw = (phi, 0)
+template <typename T>
+__global__ void k_gf_prep(Geo g, const Fld* fl, const double* Vext, const T* pot, const T* phi, T* W,
+                          V2<T>* cw, double* part_mx, double* part_mn) {
+    const int b = blockIdx.y;
+    if (fl[b].done) return;
+    const Fld f = fl[b];
+    double mx = -1e308, mn = 1e308;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        double x[3];
+        int j[3];
+        coords(g, i, x, j);
+        long long k = (long long)b * g.N + i;
+        double w = trapV(g, f, Vext, i, x) + f.beta * (double)pot[k];
+        W[k] = (T)w;
+        mx = fmax(mx, w);
+        mn = fmin(mn, w);
+        cw[k] = mkc<T>(phi[k], (T)0);
+    }
+    mx = block_max(mx);
+    mn = -block_max(-mn);
+    if (threadIdx.x == 0) {
+        part_mx[b * MAXBLK + blockIdx.x] = mx;
+        part_mn[b * MAXBLK + blockIdx.x] = mn;
+    }
+}
+
+// after FFT(phi): cw <- K cw / N  (K = |mu|^2/2)
+template <typename T>
+__global__ void k_kin_apply(Geo g, const Fld* fl, V2<T>* cw) {
+    const int b = blockIdx.y;
+    if (fl[b].done) return;
+    const double invN = 1.0 / (double)g.N;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double s = 0.5 * mu2(g, i) * invN;
+        V2<T> v = cw[k];
+        cw[k] = mkc<T>((T)(v.x * s), (T)(v.y * s));
+    }
+}
+
+// preconditioner shift a (one block per field).  The Fourier multiplier 1/(1/tau + a + K) matches
+// A = 1/tau + K + W up to the factor (1/tau + W)/(1/tau + a), which ranges over
+// [(1/tau + min W), (1/tau + max W)] / (1/tau + a); the geometric mean
+// 1/tau + a = sqrt((1/tau + min W)(1/tau + max W)) minimises the ratio of its extremes.
+__global__ void k_shift(Fld* fl, const double* part_mx, const double* part_mn, int nblk) {
+    const int b = blockIdx.x;
+    if (fl[b].done) return;
+    double mx = max_parts(part_mx + b * MAXBLK, nblk);
+    double v = (threadIdx.x < nblk) ? -part_mn[b * MAXBLK + threadIdx.x] : -1e308;
+    double mn = -block_max(v);
+    if (threadIdx.x == 0) {
+        const double it = 1.0 / fl[b].tau;
+        const double lo = it + mn, hi = it + mx;
+        fl[b].a = (lo > 0.0) ? sqrt(lo * hi) - it : 0.5 * (mx + mn);
+    }
+}
+
+// PCG start: x = phi, r = b - A x = -(K phi + W phi) (with b = phi/tau), cw = (r, 0); bb, rr partials
+template <typename T>
+__global__ void k_pcg_init(Geo g, Fld* fl, const T* phi, const T* W, const V2<T>* kphi, T* x, T* r, V2<T>* cw,
+                           double* part_bb) {
+    const int b = blockIdx.y;
+    if (fl[b].done) return;
+    const double tau = fl[b].tau;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double p = (double)phi[k];
+        double ri = -((double)kphi[k].x + (double)W[k] * p);
+        x[k] = phi[k];
+        r[k] = (T)ri;
+        cw[k] = mkc<T>((T)ri, (T)0);
+        s += (p / tau) * (p / tau);
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part_bb[b * MAXBLK + blockIdx.x] = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        fl[b].conv = 0;
+        fl[b].first = 1;
+        fl[b].rz_old = 0;
+        fl[b].cg_last = 0;
+    }
+}
+
+__global__ void k_bb_final(Fld* fl, const double* part_bb, int nblk) {
+    const int b = blockIdx.x;
+    if (fl[b].done) return;
+    double s = sum_parts(part_bb + b * MAXBLK, nblk);
+    if (threadIdx.x == 0) fl[b].bb = s;
+}
+
+// rz = sum D |r^|^2 / N (Parseval), D = 1/(1/tau + a + K)
+template <typename T>
+__global__ void k_pcg_rz(Geo g, const Fld* fl, const V2<T>* cw, double* part_rz) {
+    const int b = blockIdx.y;
+    if (fl[b].done || fl[b].conv) return;
+    const double c0 = 1.0 / fl[b].tau + fl[b].a;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        V2<T> v = cw[(long long)b * g.N + i];
+        double d = 1.0 / (c0 + 0.5 * mu2(g, i));
+        s += d * ((double)v.x * v.x + (double)v.y * v.y);
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part_rz[b * MAXBLK + blockIdx.x] = s / (double)g.N;
+}
+
+// p^ = D r^ + beta p^ (beta = rz / rz_old), cw = (p^ + i K p^) / N for the inverse transform
+template <typename T>
+__global__ void k_pcg_dir(Geo g, Fld* fl, V2<T>* cw, V2<T>* ph, const double* part_rz, int nblk) {
+    const int b = blockIdx.y;
+    if (fl[b].done || fl[b].conv) return;
+    const double rz = sum_parts(part_rz + b * MAXBLK, nblk);
+    const double rzo = fl[b].rz_old;
+    const double beta = (fl[b].first || !(rzo > 0.0)) ? 0.0 : rz / rzo;
+    const double c0 = 1.0 / fl[b].tau + fl[b].a;
+    const double invN = 1.0 / (double)g.N;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double m2 = mu2(g, i);
+        double d = 1.0 / (c0 + 0.5 * m2);
+        V2<T> rv = cw[k];
+        double px = d * (double)rv.x, py = d * (double)rv.y;
+        if (beta != 0.0) {   // the previous direction is never read on a restart (it may be unset)
+            V2<T> pv = ph[k];
+            px += beta * (double)pv.x;
+            py += beta * (double)pv.y;
+        }
+        ph[k] = mkc<T>((T)px, (T)py);
+        double kk = 0.5 * m2;
+        // (p^ + i K p^) = (px - K py, py + K px)
+        cw[k] = mkc<T>((T)((px - kk * py) * invN), (T)((py + kk * px) * invN));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) fl[b].rz = rz;
+}
+
+// p = Re cw, K p = Im cw; Ap = K p + (1/tau + W) p; pAp partials
+template <typename T>
+__global__ void k_pcg_apply(Geo g, const Fld* fl, const V2<T>* cw, const T* W, T* p, T* Ap, double* part_pap) {
+    const int b = blockIdx.y;
+    if (fl[b].done || fl[b].conv) return;
+    const double it = 1.0 / fl[b].tau;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        V2<T> v = cw[k];
+        double pv = (double)v.x;
+        double ap = (double)v.y + (it + (double)W[k]) * pv;
+        p[k] = (T)pv;
+        Ap[k] = (T)ap;
+        s += pv * ap;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part_pap[b * MAXBLK + blockIdx.x] = s;
+}
+
+// a = rz / pAp; x += a p; r -= a Ap; cw = (r, 0); rr partials
+template <typename T>
+__global__ void k_pcg_update(Geo g, const Fld* fl, const T* p, const T* Ap, T* x, T* r, V2<T>* cw,
+                             const double* part_pap, double* part_rr, int nblk) {
+    const int b = blockIdx.y;
+    if (fl[b].done || fl[b].conv) return;
+    const double pap = sum_parts(part_pap + b * MAXBLK, nblk);
+    // breakdown guard: A is symmetric positive definite, so pAp <= 0 (or a non-finite value) only
+    // happens once rounding dominates the residual; the iterate is kept and the solve stops
+    if (!(pap > 0.0) || !(fl[b].rz > 0.0) || !(pap < 1e300)) {
+        if (threadIdx.x == 0) part_rr[b * MAXBLK + blockIdx.x] = -1.0;
+        return;
+    }
+    const double al = fl[b].rz / pap;
+    double s = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double xv = (double)x[k] + al * (double)p[k];
+        double rv = (double)r[k] - al * (double)Ap[k];
+        x[k] = (T)xv;
+        r[k] = (T)rv;
+        cw[k] = mkc<T>((T)rv, (T)0);
+        s += rv * rv;
+    }
+    s = block_sum(s);
+    if (threadIdx.x == 0) part_rr[b * MAXBLK + blockIdx.x] = s;
+}
+
+__global__ void k_pcg_check(Fld* fl, const double* part_rr, int nblk) {
+    const int b = blockIdx.x;
+    if (fl[b].done || fl[b].conv) return;
+    double rr = sum_parts(part_rr + b * MAXBLK, nblk);
+    // a negative partial marks a breakdown stop of the update kernel (see k_pcg_update)
+    double mn = -max_parts_neg(part_rr + b * MAXBLK, nblk);
+    if (threadIdx.x == 0) {
+        fl[b].rr = rr;
+        fl[b].rz_old = fl[b].rz;
+        fl[b].first = 0;
+        fl[b].cg_iters += 1;
+        fl[b].cg_last += 1;
+        const double tol = fl[b].cgtol;
+        if (mn < 0.0) fl[b].conv = 1;
+        else if (!(rr == rr) || rr > 1e300) {
+            fl[b].nonfinite = 1;
+            fl[b].conv = 1;
+        } else if (rr <= tol * tol * fl[b].bb) fl[b].conv = 1;
+    }
+}
+
+// energies: partials of [Ekin, Epot, Eint, mass] (Ekin from |mu|^2 |phi^|^2 in Fourier space)
+template <typename T>
+__global__ void k_energy_part(Geo g, const Fld* fl, const double* Vext, const V2<T>* psi_hat, const V2<T>* psi_c,
+                              const T* psi_r, const T* pot, double* part, int nblk_stride) {
+    const int b = blockIdx.y;
+    const Fld f = fl[b];
+    double ek = 0, ep = 0, ei = 0, ms = 0;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double x[3];
+        int j[3];
+        coords(g, i, x, j);
+        V2<T> hv = psi_hat[k];
+        ek += mu2(g, i) * ((double)hv.x * hv.x + (double)hv.y * hv.y);
+        double dens;
+        if (psi_c) {
+            V2<T> v = psi_c[k];
+            dens = (double)v.x * v.x + (double)v.y * v.y;
+        } else {
+            double v = (double)psi_r[k];
+            dens = v * v;
+        }
+        ep += trapV(g, f, Vext, i, x) * dens;
+        ei += (double)pot[k] * dens;
+        ms += dens;
+    }
+    ek = block_sum(ek);
+    ep = block_sum(ep);
+    ei = block_sum(ei);
+    ms = block_sum(ms);
+    if (threadIdx.x == 0) {
+        double* o = part + ((long long)b * nblk_stride + blockIdx.x) * 4;
+        o[0] = 0.5 * g.dv * ek / (double)g.N;
+        o[1] = g.dv * ep;
+        o[2] = 0.5 * f.beta * g.dv * ei;
+        o[3] = g.dv * ms;
+    }
+}
+
+template <typename T>
+__global__ void k_real_to_complex(long long count, const T* a, V2<T>* c) {
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < count; i += (long long)gridDim.x * RB_T)
+        c[i] = mkc<T>(a[i], (T)0);
+}
+
+// ---- dynamics kernels -------------------------------------------------------------------------
+// psi^ *= exp(-i |mu|^2 t / 2) / N   (exact kinetic flow over time t, with the FFT normalisation)
+template <typename T>
+__global__ void k_kin_phase(Geo g, int batch, V2<T>* psi, double t) {
+    const int b = blockIdx.y;
+    const double invN = 1.0 / (double)g.N;
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double ang = -0.5 * mu2(g, i) * t;
+        double s, c;
+        sincos(ang, &s, &c);
+        V2<T> v = psi[k];
+        double re = ((double)v.x * c - (double)v.y * s) * invN;
+        double im = ((double)v.x * s + (double)v.y * c) * invN;
+        psi[k] = mkc<T>((T)re, (T)im);
+    }
+}
+
+template <typename T>
+__global__ void k_density(long long count, const V2<T>* psi, T* rho) {
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < count; i += (long long)gridDim.x * RB_T) {
+        V2<T> v = psi[i];
+        rho[i] = (T)((double)v.x * v.x + (double)v.y * v.y);
+    }
+}
+
+// psi *= exp(-i (V + beta varphi) t)
+template <typename T>
+__global__ void k_pot_phase(Geo g, const Fld* fl, const double* Vext, const T* pot, V2<T>* psi, double t) {
+    const int b = blockIdx.y;
+    const Fld f = fl[b];
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
+        long long k = (long long)b * g.N + i;
+        double x[3];
+        int j[3];
+        coords(g, i, x, j);
+        double ang = -(trapV(g, f, Vext, i, x) + f.beta * (double)pot[k]) * t;
+        double s, c;
+        sincos(ang, &s, &c);
+        V2<T> v = psi[k];
+        psi[k] = mkc<T>((T)((double)v.x * c - (double)v.y * s), (T)((double)v.x * s + (double)v.y * c));
+    }
+}
+
+template <typename T>
+__global__ void k_copy_c(long long count, const V2<T>* a, V2<T>* b) {
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < count; i += (long long)gridDim.x * RB_T) b[i] = a[i];
+}
+
+// ---- host side ----------------------------------------------------------------------------------
+struct SolverWs {
+    void* phi = nullptr;   // real [B][N] (GS) / unused
+    void* x = nullptr;
+    void* r = nullptr;
+    void* p = nullptr;
+    void* Ap = nullptr;
+    void* W = nullptr;
+    void* rho = nullptr;
+    void* pot = nullptr;
+    void* cw = nullptr;    // complex [B][N]
+    void* ph = nullptr;    // complex [B][N]
+    Fld* fl = nullptr;
+    double* part = nullptr;    // 8 arrays of [B][MAXBLK]
+    double* epart = nullptr;   // [B][MAXBLK][4]
+};
+
+static int ws_get(nlf_plan* p, SolverWs& w) {
+    const size_t es = elem_size(p->prec) / 2, ec = elem_size(p->prec);
+    const size_t B = p->batch, N = p->N;
+    NLF_TRY(dev_alloc(p, &w.phi, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.x, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.r, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.p, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.Ap, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.W, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.rho, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.pot, B * N * es));
+    NLF_TRY(dev_alloc(p, &w.cw, B * N * ec));
+    NLF_TRY(dev_alloc(p, &w.ph, B * N * ec));
+    NLF_TRY(dev_alloc(p, (void**)&w.fl, B * sizeof(Fld)));
+    NLF_TRY(dev_alloc(p, (void**)&w.part, 8 * B * MAXBLK * sizeof(double)));
+    NLF_TRY(dev_alloc(p, (void**)&w.epart, B * MAXBLK * 4 * sizeof(double)));
+    return NLF_OK;
+}
+
+static Geo geo_of(const nlf_plan* p) {
+    Geo g{};
+    g.dim = p->dim;
+    g.N = p->N;
+    g.dv = 1;
+    for (int i = 0; i < 3; ++i) {
+        g.n[i] = p->n[i];
+        g.L[i] = p->L[i];
+        g.h[i] = p->h[i];
+    }
+    for (int i = 0; i < p->dim; ++i) g.dv *= p->h[i];
+    return g;
+}
+
+static int nblocks(const nlf_plan* p) { return (int)std::min<long long>((p->N + RB_T - 1) / RB_T, MAXBLK); }
+
+static void sws_delete(void* q) { delete static_cast<SolverWs*>(q); }
+
+static int solver_ws(nlf_plan* p, SolverWs** out) {
+    if (!p->sws) {
+        SolverWs* w = new (std::nothrow) SolverWs();
+        if (!w) return set_error(NLF_ENOMEM, "host allocation failed");
+        int st = ws_get(p, *w);
+        if (st != NLF_OK) {
+            delete w;
+            return st;
+        }
+        p->sws = w;
+        p->sws_free = sws_delete;
+    }
+    *out = static_cast<SolverWs*>(p->sws);
+    return NLF_OK;
+}
+
+static dim3 flat_grid(long long count) {
+    return dim3((unsigned)std::max<long long>(1, std::min<long long>((count + RB_T - 1) / RB_T, 4096)));
+}
+
+// Energies of the fields: rho must hold |psi|^2 unless psi_c is given; out[b*4+q] = Ekin, Epot,
+// Eint, mass.
+template <typename T>
+static int energies_t(nlf_plan* p, const Geo& g, SolverWs& w, const double* Vext, const void* psi_c,
+                      const void* psi_r, std::vector<double>& out) {
+    const int B = p->batch, nb = nblocks(p);
+    const long long cnt = (long long)B * g.N;
+    if (psi_c) {
+        hipLaunchKernelGGL((k_density<T>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const V2<T>*)psi_c, (T*)w.rho);
+        hipLaunchKernelGGL((k_copy_c<T>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const V2<T>*)psi_c, (V2<T>*)w.cw);
+    } else {
+        hipLaunchKernelGGL((k_real_to_complex<T>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const T*)psi_r,
+                           (V2<T>*)w.cw);
+    }
+    NLF_HIP(hipGetLastError());
+    NLF_TRY(potential(p, w.rho, w.pot));
+    NLF_TRY(fft_full(p, w.cw, -1, B));
+    hipLaunchKernelGGL((k_energy_part<T>), dim3(nb, B), dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const V2<T>*)w.cw,
+                       (const V2<T>*)psi_c, (const T*)psi_r, (const T*)w.pot, w.epart, nb);
+    NLF_HIP(hipGetLastError());
+    std::vector<double> h((size_t)B * nb * 4);
+    NLF_HIP(hipMemcpyAsync(h.data(), w.epart, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    out.assign((size_t)B * 4, 0.0);
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < nb; ++i)
+            for (int q = 0; q < 4; ++q) out[b * 4 + q] += h[((size_t)b * nb + i) * 4 + q];
+    return NLF_OK;
+}
+
+static int read_flds(nlf_plan* p, SolverWs& w, std::vector<Fld>& fh) {
+    NLF_HIP(hipMemcpyAsync(fh.data(), w.fl, fh.size() * sizeof(Fld), hipMemcpyDeviceToHost, p->stream));
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    return NLF_OK;
+}
+
+template <typename T>
+static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* gf, const void* psi0, void* psi,
+                          nlf_gs_stats* stats) {
+    SolverWs* wp;
+    NLF_TRY(solver_ws(p, &wp));
+    SolverWs& w = *wp;
+    const int B = p->batch, nb = nblocks(p);
+    const Geo g = geo_of(p);
+    const double tau = (gf && gf->tau > 0) ? gf->tau : 1e-2;
+    const double eps0 = (gf && gf->eps0 > 0) ? gf->eps0 : 1e-10;
+    const int max_iter = (gf && gf->max_iter > 0) ? gf->max_iter : 100000;
+    const int check_every = (gf && gf->check_every > 0) ? gf->check_every : 10;
+    const double cg_tol = (gf && gf->cg_tol > 0) ? gf->cg_tol : (p->prec == NLF_F64 ? 1e-13 : 1e-6);
+    const int cg_max = (gf && gf->cg_max_iter > 0) ? gf->cg_max_iter : 200;
+    const double* Vext = (const double*)phys[0].V_dev;
+
+    std::vector<Fld> fh(B);
+    for (int b = 0; b < B; ++b) {
+        std::memset(&fh[b], 0, sizeof(Fld));
+        fh[b].beta = phys[b].beta;
+        for (int a = 0; a < 3; ++a) {
+            double ga = (a < p->dim) ? phys[b].gamma[a] : 0.0;
+            if (a < p->dim && !(ga > 0)) return set_error(NLF_EINVAL, "gamma[%d] of field %d must be positive", a, b);
+            fh[b].g2[a] = ga * ga;
+        }
+        fh[b].tau = tau;
+        fh[b].cgtol_min = cg_tol;
+        fh[b].cgtol = std::max(cg_tol, 1e-3);
+    }
+    NLF_HIP(hipMemcpyAsync(w.fl, fh.data(), B * sizeof(Fld), hipMemcpyHostToDevice, p->stream));
+    const dim3 grid(nb, B);
+    const size_t rbytes = (size_t)B * g.N * (elem_size(p->prec) / 2);
+    double* part_n = w.part;
+    double* part_r = w.part + 1 * B * MAXBLK;
+    double* part_mx = w.part + 2 * B * MAXBLK;
+    double* part_mn = w.part + 3 * B * MAXBLK;
+    double* part_bb = w.part + 4 * B * MAXBLK;
+    double* part_rz = w.part + 5 * B * MAXBLK;
+    double* part_pap = w.part + 6 * B * MAXBLK;
+    double* part_rr = w.part + 7 * B * MAXBLK;
+
+    if (psi0) NLF_HIP(hipMemcpyAsync(w.phi, psi0, rbytes, hipMemcpyDeviceToDevice, p->stream));
+    else hipLaunchKernelGGL((k_ho_init<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (T*)w.phi);
+    hipLaunchKernelGGL((k_norm2_part<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.phi, part_n);
+    hipLaunchKernelGGL((k_normalize<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.phi, (T*)w.phi,
+                       (T*)w.rho, part_n, part_r, nb, 0);
+    NLF_HIP(hipGetLastError());
+
+    int it = 0;
+    bool all_done = false;
+    int last_cg = 4;
+    for (it = 1; it <= max_iter && !all_done; ++it) {
+        NLF_TRY(potential(p, w.rho, w.pot));
+        hipLaunchKernelGGL((k_gf_prep<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const T*)w.pot,
+                           (const T*)w.phi, (T*)w.W, (V2<T>*)w.cw, part_mx, part_mn);
+        hipLaunchKernelGGL(k_shift, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_mx, part_mn, nb);
+        NLF_TRY(fft_full(p, w.cw, -1, B));
+        hipLaunchKernelGGL((k_kin_apply<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (V2<T>*)w.cw);
+        NLF_TRY(fft_full(p, w.cw, 1, B));
+        hipLaunchKernelGGL((k_pcg_init<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.phi, (const T*)w.W,
+                           (const V2<T>*)w.cw, (T*)w.x, (T*)w.r, (V2<T>*)w.cw, part_bb);
+        hipLaunchKernelGGL(k_bb_final, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_bb, nb);
+        NLF_HIP(hipGetLastError());
+        // convergence is read back first after about as many iterations as the previous solve took,
+        // then every second iteration (each read is a stream synchronisation)
+        int next_check = std::max(2, last_cg - 1);
+        int most = 0;
+        for (int cg = 0; cg < cg_max; ++cg) {
+            NLF_TRY(fft_full(p, w.cw, -1, B));
+            hipLaunchKernelGGL((k_pcg_rz<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.cw, part_rz);
+            hipLaunchKernelGGL((k_pcg_dir<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (V2<T>*)w.cw, (V2<T>*)w.ph,
+                               part_rz, nb);
+            NLF_TRY(fft_full(p, w.cw, 1, B));
+            hipLaunchKernelGGL((k_pcg_apply<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.cw,
+                               (const T*)w.W, (T*)w.p, (T*)w.Ap, part_pap);
+            hipLaunchKernelGGL((k_pcg_update<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.p,
+                               (const T*)w.Ap, (T*)w.x, (T*)w.r, (V2<T>*)w.cw, part_pap, part_rr, nb);
+            hipLaunchKernelGGL(k_pcg_check, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_rr, nb);
+            NLF_HIP(hipGetLastError());
+            if (cg + 1 >= next_check) {
+                NLF_TRY(read_flds(p, w, fh));
+                bool all = true;
+                for (int b = 0; b < B; ++b) {
+                    all = all && (fh[b].done || fh[b].conv);
+                    most = std::max(most, fh[b].cg_last);
+                }
+                if (all) break;
+                next_check = cg + 3;
+            }
+        }
+        last_cg = most;
+        hipLaunchKernelGGL((k_norm2_part<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, part_n);
+        hipLaunchKernelGGL((k_normalize<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, (T*)w.phi,
+                           (T*)w.rho, part_n, part_r, nb, 1);
+        hipLaunchKernelGGL((k_residual_final<T>), dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_r, nb, eps0);
+        NLF_HIP(hipGetLastError());
+        if (it % check_every == 0 || it == max_iter) {
+            NLF_TRY(read_flds(p, w, fh));
+            all_done = true;
+            for (int b = 0; b < B; ++b) {
+                if (fh[b].nonfinite) return set_error(NLF_ENONFINITE, "non-finite value in field %d at step %d", b, it);
+                all_done = all_done && fh[b].done;
+            }
+        }
+    }
+    NLF_TRY(read_flds(p, w, fh));
+    // final energies (rho holds phi^2 from the last normalisation)
+    std::vector<double> e;
+    NLF_TRY(energies_t<T>(p, g, w, Vext, nullptr, w.phi, e));
+    bool all = true;
+    for (int b = 0; b < B; ++b) {
+        nlf_gs_stats& st = stats[b];
+        st.iters = it - 1;
+        st.cg_iters = fh[b].cg_iters;
+        st.Ekin = e[b * 4 + 0];
+        st.Epot = e[b * 4 + 1];
+        st.Eint = e[b * 4 + 2];
+        st.mass = e[b * 4 + 3];
+        st.E = st.Ekin + st.Epot + st.Eint;
+        st.mu = st.E + st.Eint;
+        st.residual = fh[b].res;
+        st.virial = 2.0 * st.Ekin - 2.0 * st.Epot +
+                    (p->kernel == NLF_LAPLACE2D ? phys[b].beta / (4.0 * 3.14159265358979323846) : st.Eint);
+        all = all && fh[b].done;
+    }
+    NLF_HIP(hipMemcpyAsync(psi, w.phi, rbytes, hipMemcpyDeviceToDevice, p->stream));
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    if (!all) return set_error(NLF_ENOCONV, "gradient flow did not reach eps0 = %g within %d steps", eps0, max_iter);
+    return NLF_OK;
+}
+
+template <typename T>
+static int evolve_t(nlf_plan* p, const nlf_phys* phys, const nlf_ts_opts* ts, void* psi, double* diag) {
+    SolverWs* wp;
+    NLF_TRY(solver_ws(p, &wp));
+    SolverWs& w = *wp;
+    const int B = p->batch, nb = nblocks(p);
+    const Geo g = geo_of(p);
+    const double dt = ts->dt;
+    const int nsteps = ts->nsteps, order = ts->order ? ts->order : 2, de = ts->diag_every;
+    if (!(dt > 0) || nsteps < 0 || (order != 2 && order != 4) || de < 0)
+        return set_error(NLF_EINVAL, "need dt > 0, nsteps >= 0, order 2 or 4, diag_every >= 0");
+    const double* Vext = (const double*)phys[0].V_dev;
+    std::vector<Fld> fh(B);
+    for (int b = 0; b < B; ++b) {
+        std::memset(&fh[b], 0, sizeof(Fld));
+        fh[b].beta = phys[b].beta;
+        for (int a = 0; a < 3; ++a) fh[b].g2[a] = (a < p->dim) ? phys[b].gamma[a] * phys[b].gamma[a] : 0.0;
+    }
+    NLF_HIP(hipMemcpyAsync(w.fl, fh.data(), B * sizeof(Fld), hipMemcpyHostToDevice, p->stream));
+    const dim3 grid(nb, B);
+    const long long cnt = (long long)B * g.N;
+    double pending = 0.0;   // kinetic time not yet applied (adjacent half steps are merged)
+
+    auto flush_kin = [&]() -> int {
+        if (pending != 0.0) {
+            NLF_TRY(fft_full(p, psi, -1, B));
+            hipLaunchKernelGGL((k_kin_phase<T>), grid, dim3(RB_T), 0, p->stream, g, B, (V2<T>*)psi, pending);
+            NLF_HIP(hipGetLastError());
+            NLF_TRY(fft_full(p, psi, 1, B));
+            pending = 0.0;
+        }
+        return NLF_OK;
+    };
+    auto strang = [&](double t) -> int {
+        pending += 0.5 * t;
+        NLF_TRY(flush_kin());
+        hipLaunchKernelGGL((k_density<T>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const V2<T>*)psi, (T*)w.rho);
+        NLF_HIP(hipGetLastError());
+        NLF_TRY(potential(p, w.rho, w.pot));
+        hipLaunchKernelGGL((k_pot_phase<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const T*)w.pot,
+                           (V2<T>*)psi, t);
+        NLF_HIP(hipGetLastError());
+        pending += 0.5 * t;
+        return NLF_OK;
+    };
+    auto record = [&](int slot) -> int {
+        NLF_TRY(flush_kin());
+        std::vector<double> e;
+        NLF_TRY(energies_t<T>(p, g, w, Vext, psi, nullptr, e));
+        for (int b = 0; b < B; ++b) {
+            diag[((size_t)slot * B + b) * 2 + 0] = e[b * 4 + 3];
+            diag[((size_t)slot * B + b) * 2 + 1] = e[b * 4 + 0] + e[b * 4 + 1] + e[b * 4 + 2];
+        }
+        return NLF_OK;
+    };
+    const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = -std::cbrt(2.0) / (2.0 - std::cbrt(2.0));
+    int slot = 0;
+    if (de && diag) NLF_TRY(record(slot++));
+    for (int s = 1; s <= nsteps; ++s) {
+        if (order == 2) NLF_TRY(strang(dt));
+        else {
+            NLF_TRY(strang(w1 * dt));
+            NLF_TRY(strang(w0 * dt));
+            NLF_TRY(strang(w1 * dt));
+        }
+        if (de && diag && s % de == 0) NLF_TRY(record(slot++));
+    }
+    NLF_TRY(flush_kin());
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    return NLF_OK;
+}
+
+}  // namespace nlf
 
 using namespace nlf;
 
 extern "C" {
 
-int nlf_ground_state(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* gf, const void* psi0,
-                     void* psi, nlf_gs_stats* stats) {
+int nlf_ground_state(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* gf, const void* psi0, void* psi,
+                     nlf_gs_stats* stats) {
     clear_error();
-    (void)p; (void)phys; (void)gf; (void)psi0; (void)psi; (void)stats;
-    return set_error(NLF_EUNSUPPORTED, "ground state solver not built yet");
+    if (!p || !phys || !psi || !stats) return set_error(NLF_EINVAL, "plan, phys, psi and stats must not be NULL");
+    return p->prec == NLF_F64 ? ground_state_t<double>(p, phys, gf, psi0, psi, stats)
+                              : ground_state_t<float>(p, phys, gf, psi0, psi, stats);
 }
 
 int nlf_evolve(nlf_plan* p, const nlf_phys* phys, const nlf_ts_opts* ts, void* psi, double* diag) {
     clear_error();
-    (void)p; (void)phys; (void)ts; (void)psi; (void)diag;
-    return set_error(NLF_EUNSUPPORTED, "dynamics solver not built yet");
+    if (!p || !phys || !ts || !psi) return set_error(NLF_EINVAL, "plan, phys, ts and psi must not be NULL");
+    return p->prec == NLF_F64 ? evolve_t<double>(p, phys, ts, psi, diag) : evolve_t<float>(p, phys, ts, psi, diag);
 }
 
 }  // extern "C"

@@ -18,7 +18,9 @@ COULOMB3D, COULOMB2D, LAPLACE2D = 1, 2, 3
 
 EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan_nodes",
            "nlf_potential", "nlf_type2", "nlf_type1", "nlf_ground_state", "nlf_evolve",
-           "nlf_last_error", "nlf_strerror", "nlf_version"]
+           "nlf_last_error", "nlf_strerror", "nlf_version", "nlf_plan_set_profiling",
+           "nlf_plan_stage_times"]
+STAGES = ["moments", "fft_fwd", "interp", "zero", "spread", "fft_inv"]
 
 
 class Box(ctypes.Structure):
@@ -88,6 +90,8 @@ def load(path=LIB_PATH):
     lib.nlf_ground_state.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(GfOpts), vp, vp,
                                      ctypes.POINTER(GsStats)]
     lib.nlf_evolve.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(TsOpts), vp, dp]
+    lib.nlf_plan_set_profiling.argtypes = [vp, ip]
+    lib.nlf_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ip]
     for f in ["nlf_last_error", "nlf_strerror", "nlf_version"]:
         getattr(lib, f).restype = ctypes.c_char_p
     lib.nlf_strerror.argtypes = [ip]
@@ -166,6 +170,16 @@ class Plan:
                                      w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return k, w
 
+    def set_profiling(self, on):
+        _check(load().nlf_plan_set_profiling(self._h, 1 if on else 0))
+
+    def stage_times(self, reset=True):
+        """{stage: (total ms, launches)} since the last reset (synchronises the plan's stream)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_longlong * len(STAGES))()
+        _check(load().nlf_plan_stage_times(self._h, ms, cnt, 1 if reset else 0))
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
     def _shape(self):
         return (self.batch,) + self.n if self.batch > 1 else self.n
 
@@ -200,14 +214,26 @@ class Plan:
         _check(load().nlf_type1(self._h, _ptr(c), _ptr(out)))
         return out
 
+    def _phys(self, beta, gamma, V):
+        """Host array of `batch` nlf_phys entries; beta / gamma may be per-field lists."""
+        betas = list(beta) if np.ndim(beta) else [beta] * self.batch
+        gams = list(gamma) if np.ndim(gamma) == 2 else [gamma] * self.batch
+        if len(betas) != self.batch or len(gams) != self.batch:
+            raise ValueError("beta / gamma must give one entry per batch field")
+        arr = (Phys * self.batch)()
+        for b in range(self.batch):
+            arr[b].beta = float(betas[b])
+            for i, g in enumerate(gams[b]):
+                arr[b].gamma[i] = float(g)
+            arr[b].V_dev = V.data_ptr() if V is not None else None
+        return arr
+
     def ground_state(self, beta, gamma, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
                      cg_tol=0.0, cg_max_iter=0, psi0=None, V=None, out=None):
         """nlf_ground_state; returns (psi, [stats dict per field], status)."""
-        phys = Phys()
-        phys.beta = float(beta)
-        for i, g in enumerate(gamma):
-            phys.gamma[i] = float(g)
-        phys.V_dev = V.data_ptr() if V is not None else None
+        phys = self._phys(beta, gamma, V)
+        if V is not None:
+            self._check_in(V, self.torch.float64, int(np.prod(self.n)))
         gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter)
         N = int(np.prod(self.n)) * self.batch
         if psi0 is not None:
@@ -215,25 +241,23 @@ class Plan:
         if out is None:
             out = self.torch.empty(self._shape(), dtype=self.rdtype, device="cuda")
         stats = (GsStats * self.batch)()
-        st = load().nlf_ground_state(self._h, ctypes.byref(phys), ctypes.byref(gf), _ptr(psi0),
-                                     _ptr(out), stats)
+        st = load().nlf_ground_state(self._h, phys, ctypes.byref(gf), _ptr(psi0), _ptr(out), stats)
         if st not in (OK, ENOCONV):
             _check(st)
         return out, [s.as_dict() for s in stats], st
 
     def evolve(self, psi, beta, gamma, dt, nsteps, order=2, diag_every=0, V=None):
-        """nlf_evolve in place on psi (complex); returns diagnostics (mass, energy) array or None."""
+        """nlf_evolve in place on psi (complex); returns diagnostics [slot][field][(mass, energy)]
+        or None."""
         self._check_in(psi, self.cdtype, int(np.prod(self.n)) * self.batch)
-        phys = Phys()
-        phys.beta = float(beta)
-        for i, g in enumerate(gamma):
-            phys.gamma[i] = float(g)
-        phys.V_dev = V.data_ptr() if V is not None else None
+        if V is not None:
+            self._check_in(V, self.torch.float64, int(np.prod(self.n)))
+        phys = self._phys(beta, gamma, V)
         ts = TsOpts(dt, nsteps, order, diag_every)
         diag = None
         dptr = ctypes.POINTER(ctypes.c_double)()
         if diag_every:
             diag = np.zeros((nsteps // diag_every + 1, self.batch, 2))
             dptr = diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        _check(load().nlf_evolve(self._h, ctypes.byref(phys), ctypes.byref(ts), _ptr(psi), dptr))
+        _check(load().nlf_evolve(self._h, phys, ctypes.byref(ts), _ptr(psi), dptr))
         return diag
