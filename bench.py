@@ -136,18 +136,24 @@ def stage_algorithmic(plan, stage):
 
 
 def load_traffic(kernel_stage):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken on the
-    current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    """HBM bytes per launch of a stage from the committed rocprofv3 --pmc summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the reading for a plain copy of known size), if that summary was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_potential_2d512.txt")
+    vals = {}
     try:
         with open(path) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            for line in f:
+                line = line.split("#")[0].strip()
+                if "=" in line:
+                    k, v = line.split("=", 1)
+                    vals[k.strip()] = v.strip()
+    except OSError:
         return None
-    if t.get("sources") != kernel_sources_hash():
+    if vals.get("sources") != kernel_sources_hash():
         return None
-    ent = t.get("stages", {}).get(kernel_stage)
-    return None if ent is None else ent.get("bytes_per_launch")
+    v = vals.get(f"traffic_{kernel_stage}")
+    return None if v is None else float(v)
 
 
 def main():
