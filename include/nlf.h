@@ -152,16 +152,24 @@ typedef struct {
 /* Gradient-flow options (Sec. 3.1/3.2).  tau: time step (default 1e-2); eps0: stopping
  * tolerance on max|phi^{n+1}-phi^n|/tau (default 1e-10); max_iter (default 100000);
  * check_every: outer steps between host convergence checks (default 10);
- * cg_tol: relative residual of the inner linear solve (default 1e-13 FP64, 1e-7 FP32).      */
+ * cg_tol: final relative residual of the inner linear solve (default 1e-13 FP64, 1e-6 FP32; the
+ * tolerance of each solve follows the outer residual down to it); cg_max_iter (default 200);
+ * mixed: with an FP32 plan, run the flow in FP32 until the residual reaches eps_switch (default
+ * 1e-5) or stops decreasing, then finish in FP64 on an FP64 twin of the plan (created on first
+ * use, owned by the plan) down to eps0.  Energies are then those of the FP64 state; psi_dev is
+ * returned rounded to the plan's precision.                                                 */
 typedef struct {
     double tau, eps0;
     int    max_iter, check_every;
     double cg_tol;
     int    cg_max_iter;
+    int    mixed;
+    double eps_switch;
 } nlf_gf_opts;
 
 typedef struct {
-    int    iters;           /* outer gradient-flow steps taken                              */
+    int    iters;           /* outer gradient-flow steps taken (all precisions)             */
+    int    iters_fp32;      /* of which in FP32 (mixed schedule)                            */
     int    cg_iters;        /* inner linear-solver iterations, summed                       */
     double E, mu, Ekin, Epot, Eint;
     double residual;        /* last max|phi^{n+1}-phi^n|/tau                                 */
@@ -180,6 +188,16 @@ typedef struct {
  * Returns NLF_ENOCONV if any field hit max_iter (stats still filled).                       */
 int nlf_ground_state(nlf_plan* plan, const nlf_phys* phys, const nlf_gf_opts* gf,
                      const void* psi0_dev, void* psi_dev, nlf_gs_stats* stats);
+
+/* Several ground-state solves at once, e.g. one plan per grid size of a batch of instances of
+ * uneven size: plan i (with its own batch B_i) takes phys[i] (B_i entries), psi0_dev[i] (or NULL),
+ * psi_dev[i] and stats[i] (B_i entries), exactly as nlf_ground_state.  The solves run
+ * concurrently, one host thread per plan; give the plans distinct streams so that their kernels
+ * overlap on the device.  Returns the first error, else NLF_ENOCONV if any field did not reach
+ * eps0, else NLF_OK.                                                                         */
+int nlf_ground_state_batch(int count, nlf_plan* const plans[], const nlf_phys* const phys[],
+                           const nlf_gf_opts* gf, const void* const psi0_dev[], void* const psi_dev[],
+                           nlf_gs_stats* const stats[]);
 
 /* Time-splitting pseudospectral dynamics (Sec. 4.1, Eqs. 'sps-eq65'-'sps-eq68').
  * order 2: Strang K(dt/2) P(dt) K(dt/2); order 4: Yoshida composition of three Strang steps.

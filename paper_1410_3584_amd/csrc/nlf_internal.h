@@ -109,6 +109,11 @@ struct nlf_plan {
     long long workspace_bytes = 0;
     std::vector<void*> owned;   // every device allocation, freed on destroy
 
+    // FP64 twin of an FP32 plan for the mixed gradient-flow schedule (created on first use)
+    nlf_plan* twin = nullptr;
+    nlf_box box_copy{};
+    nlf_opts opts_copy{};
+
     // solver workspace (allocated by the first solver call; buffers are in `owned`)
     void* sws = nullptr;
     void (*sws_free)(void*) = nullptr;

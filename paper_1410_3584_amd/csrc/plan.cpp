@@ -510,6 +510,8 @@ int nlf_plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* 
     nlf_plan* p = new (std::nothrow) nlf_plan();
     if (!p) return set_error(NLF_ENOMEM, "host allocation of the plan failed");
     p->stream = (hipStream_t)stream;
+    p->box_copy = *box;
+    if (opts) p->opts_copy = *opts;
     int st;
     try {
         st = build(p, box, kernel, opts);
@@ -553,6 +555,7 @@ int nlf_plan_destroy(nlf_plan* p) {
     (void)hipStreamSynchronize(p->stream);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->sws && p->sws_free) p->sws_free(p->sws);
+    if (p->twin) nlf_plan_destroy(p->twin);
     for (void* q : p->owned) (void)hipFree(q);
     delete p;
     return NLF_OK;

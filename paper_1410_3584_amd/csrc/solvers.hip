@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "nlf_internal.h"
@@ -517,6 +519,12 @@ __global__ void k_copy_c(long long count, const V2<T>* a, V2<T>* b) {
     for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < count; i += (long long)gridDim.x * RB_T) b[i] = a[i];
 }
 
+template <typename A, typename Bt>
+__global__ void k_convert(long long count, const A* a, Bt* b) {
+    for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < count; i += (long long)gridDim.x * RB_T)
+        b[i] = (Bt)a[i];
+}
+
 // ---- host side ----------------------------------------------------------------------------------
 struct SolverWs {
     void* phi = nullptr;   // real [B][N] (GS) / unused
@@ -627,20 +635,34 @@ static int read_flds(nlf_plan* p, SolverWs& w, std::vector<Fld>& fh) {
     return NLF_OK;
 }
 
+struct GsParams {
+    double tau, eps0, cg_tol;
+    int max_iter, check_every, cg_max;
+    int stall_stop;      // retire a field whose residual stopped decreasing (precision floor)
+};
+
+static GsParams gs_params(const nlf_plan* p, const nlf_gf_opts* gf) {
+    GsParams g;
+    g.tau = (gf && gf->tau > 0) ? gf->tau : 1e-2;
+    g.eps0 = (gf && gf->eps0 > 0) ? gf->eps0 : 1e-10;
+    g.max_iter = (gf && gf->max_iter > 0) ? gf->max_iter : 100000;
+    g.check_every = (gf && gf->check_every > 0) ? gf->check_every : 10;
+    g.cg_tol = (gf && gf->cg_tol > 0) ? gf->cg_tol : (p->prec == NLF_F64 ? 1e-13 : 1e-6);
+    g.cg_max = (gf && gf->cg_max_iter > 0) ? gf->cg_max_iter : 200;
+    g.stall_stop = 0;
+    return g;
+}
+
 template <typename T>
-static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* gf, const void* psi0, void* psi,
+static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp, const void* psi0, void* psi,
                           nlf_gs_stats* stats) {
     SolverWs* wp;
     NLF_TRY(solver_ws(p, &wp));
     SolverWs& w = *wp;
     const int B = p->batch, nb = nblocks(p);
     const Geo g = geo_of(p);
-    const double tau = (gf && gf->tau > 0) ? gf->tau : 1e-2;
-    const double eps0 = (gf && gf->eps0 > 0) ? gf->eps0 : 1e-10;
-    const int max_iter = (gf && gf->max_iter > 0) ? gf->max_iter : 100000;
-    const int check_every = (gf && gf->check_every > 0) ? gf->check_every : 10;
-    const double cg_tol = (gf && gf->cg_tol > 0) ? gf->cg_tol : (p->prec == NLF_F64 ? 1e-13 : 1e-6);
-    const int cg_max = (gf && gf->cg_max_iter > 0) ? gf->cg_max_iter : 200;
+    const double tau = gp.tau, eps0 = gp.eps0, cg_tol = gp.cg_tol;
+    const int max_iter = gp.max_iter, check_every = gp.check_every, cg_max = gp.cg_max;
     const double* Vext = (const double*)phys[0].V_dev;
 
     std::vector<Fld> fh(B);
@@ -678,6 +700,8 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* 
     int it = 0;
     bool all_done = false;
     int last_cg = 4;
+    std::vector<double> best_res(B, 1e300);
+    std::vector<int> stall(B, 0), stalled(B, 0);
     for (it = 1; it <= max_iter && !all_done; ++it) {
         NLF_TRY(potential(p, w.rho, w.pot));
         hipLaunchKernelGGL((k_gf_prep<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const T*)w.pot,
@@ -726,10 +750,24 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* 
         if (it % check_every == 0 || it == max_iter) {
             NLF_TRY(read_flds(p, w, fh));
             all_done = true;
+            bool retire = false;
             for (int b = 0; b < B; ++b) {
                 if (fh[b].nonfinite) return set_error(NLF_ENONFINITE, "non-finite value in field %d at step %d", b, it);
+                if (gp.stall_stop && !fh[b].done) {
+                    // the residual of a precision-limited flow levels off at the rounding floor; a
+                    // field that has not improved by 10% over three checks is retired
+                    if (fh[b].res < 0.9 * best_res[b]) {
+                        best_res[b] = fh[b].res;
+                        stall[b] = 0;
+                    } else if (++stall[b] >= 3) {
+                        fh[b].done = 1;
+                        stalled[b] = 1;
+                        retire = true;
+                    }
+                }
                 all_done = all_done && fh[b].done;
             }
+            if (retire) NLF_HIP(hipMemcpyAsync(w.fl, fh.data(), B * sizeof(Fld), hipMemcpyHostToDevice, p->stream));
         }
     }
     NLF_TRY(read_flds(p, w, fh));
@@ -740,6 +778,7 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* 
     for (int b = 0; b < B; ++b) {
         nlf_gs_stats& st = stats[b];
         st.iters = it - 1;
+        st.iters_fp32 = (sizeof(T) == 4) ? st.iters : 0;
         st.cg_iters = fh[b].cg_iters;
         st.Ekin = e[b * 4 + 0];
         st.Epot = e[b * 4 + 1];
@@ -750,7 +789,7 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* 
         st.residual = fh[b].res;
         st.virial = 2.0 * st.Ekin - 2.0 * st.Epot +
                     (p->kernel == NLF_LAPLACE2D ? phys[b].beta / (4.0 * 3.14159265358979323846) : st.Eint);
-        all = all && fh[b].done;
+        all = all && fh[b].done && !stalled[b];
     }
     NLF_HIP(hipMemcpyAsync(psi, w.phi, rbytes, hipMemcpyDeviceToDevice, p->stream));
     NLF_HIP(hipStreamSynchronize(p->stream));
@@ -840,8 +879,86 @@ int nlf_ground_state(nlf_plan* p, const nlf_phys* phys, const nlf_gf_opts* gf, c
                      nlf_gs_stats* stats) {
     clear_error();
     if (!p || !phys || !psi || !stats) return set_error(NLF_EINVAL, "plan, phys, psi and stats must not be NULL");
-    return p->prec == NLF_F64 ? ground_state_t<double>(p, phys, gf, psi0, psi, stats)
-                              : ground_state_t<float>(p, phys, gf, psi0, psi, stats);
+    GsParams gp = gs_params(p, gf);
+    if (p->prec == NLF_F64) return ground_state_t<double>(p, phys, gp, psi0, psi, stats);
+    if (!(gf && gf->mixed)) return ground_state_t<float>(p, phys, gp, psi0, psi, stats);
+
+    // mixed schedule: FP32 down to eps_switch (or the FP32 floor), then FP64 on the twin plan
+    const double eps_final = gp.eps0;
+    GsParams g1 = gp;
+    g1.eps0 = std::max(eps_final, (gf->eps_switch > 0) ? gf->eps_switch : 1e-5);
+    g1.stall_stop = 1;
+    const int B = p->batch;
+    std::vector<nlf_gs_stats> s1(B), s2(B);
+    int st = ground_state_t<float>(p, phys, g1, psi0, psi, s1.data());
+    if (st != NLF_OK && st != NLF_ENOCONV) return st;
+    if (!p->twin) {
+        nlf_opts o = p->opts_copy;
+        o.prec = NLF_F64;
+        o.msp = 0;
+        o.batch = p->batch;
+        NLF_TRY(nlf_plan_create(&p->box_copy, p->kernel, &o, p->stream, &p->twin));
+    }
+    SolverWs* w2;
+    NLF_TRY(solver_ws(p->twin, &w2));
+    const long long cnt = (long long)B * p->N;
+    // the twin's x buffer carries the FP32 state in FP64 as the initial guess
+    hipLaunchKernelGGL((k_convert<float, double>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const float*)psi,
+                       (double*)w2->x);
+    NLF_HIP(hipGetLastError());
+    GsParams g2 = gs_params(p->twin, gf);
+    g2.eps0 = eps_final;
+    int used = 0;
+    for (int b = 0; b < B; ++b) used = std::max(used, s1[b].iters);
+    g2.max_iter = std::max(1, gp.max_iter - used);
+    st = ground_state_t<double>(p->twin, phys, g2, w2->x, w2->Ap, s2.data());
+    if (st != NLF_OK && st != NLF_ENOCONV) return st;
+    hipLaunchKernelGGL((k_convert<double, float>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const double*)w2->Ap,
+                       (float*)psi);
+    NLF_HIP(hipGetLastError());
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    for (int b = 0; b < B; ++b) {
+        stats[b] = s2[b];
+        stats[b].iters = s1[b].iters + s2[b].iters;
+        stats[b].iters_fp32 = s1[b].iters;
+        stats[b].cg_iters = s1[b].cg_iters + s2[b].cg_iters;
+    }
+    if (st == NLF_ENOCONV) return set_error(NLF_ENOCONV, "mixed-precision gradient flow did not reach eps0 = %g", eps_final);
+    return NLF_OK;
+}
+
+int nlf_ground_state_batch(int count, nlf_plan* const plans[], const nlf_phys* const phys[], const nlf_gf_opts* gf,
+                           const void* const psi0[], void* const psi[], nlf_gs_stats* const stats[]) {
+    clear_error();
+    if (count < 0 || (count > 0 && (!plans || !phys || !psi || !stats)))
+        return set_error(NLF_EINVAL, "count must be >= 0 and the arrays non-NULL");
+    for (int i = 0; i < count; ++i)
+        if (!plans[i] || !phys[i] || !psi[i] || !stats[i]) return set_error(NLF_EINVAL, "entry %d has a NULL pointer", i);
+    int dev = 0;
+    NLF_HIP(hipGetDevice(&dev));
+    std::vector<int> status(count, NLF_OK);
+    std::vector<std::string> msg(count);
+    std::vector<std::thread> th;
+    for (int i = 0; i < count; ++i) {
+        th.emplace_back([&, i]() {
+            if (hipSetDevice(dev) != hipSuccess) {
+                status[i] = NLF_EHIP;
+                msg[i] = "hipSetDevice failed in a solver thread";
+                return;
+            }
+            status[i] = nlf_ground_state(plans[i], phys[i], gf, psi0 ? psi0[i] : nullptr, psi[i], stats[i]);
+            msg[i] = nlf_last_error();
+        });
+    }
+    for (auto& t : th) t.join();
+    int noconv = -1;
+    for (int i = 0; i < count; ++i) {
+        if (status[i] != NLF_OK && status[i] != NLF_ENOCONV)
+            return set_error(status[i], "plan %d: %s", i, msg[i].c_str());
+        if (status[i] == NLF_ENOCONV && noconv < 0) noconv = i;
+    }
+    if (noconv >= 0) return set_error(NLF_ENOCONV, "plan %d: %s", noconv, msg[noconv].c_str());
+    return NLF_OK;
 }
 
 int nlf_evolve(nlf_plan* p, const nlf_phys* phys, const nlf_ts_opts* ts, void* psi, double* diag) {

@@ -17,7 +17,8 @@ F64, F32 = 0, 1
 COULOMB3D, COULOMB2D, LAPLACE2D = 1, 2, 3
 
 EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan_nodes",
-           "nlf_potential", "nlf_type2", "nlf_type1", "nlf_ground_state", "nlf_evolve",
+           "nlf_potential", "nlf_type2", "nlf_type1", "nlf_ground_state", "nlf_ground_state_batch",
+           "nlf_evolve",
            "nlf_last_error", "nlf_strerror", "nlf_version", "nlf_plan_set_profiling",
            "nlf_plan_stage_times"]
 STAGES = ["moments", "fft_fwd", "interp", "zero", "spread", "fft_inv"]
@@ -48,11 +49,13 @@ class Phys(ctypes.Structure):
 
 class GfOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("eps0", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int),
+                ("mixed", ctypes.c_int), ("eps_switch", ctypes.c_double)]
 
 
 class GsStats(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int), ("cg_iters", ctypes.c_int), ("E", ctypes.c_double),
+    _fields_ = [("iters", ctypes.c_int), ("iters_fp32", ctypes.c_int), ("cg_iters", ctypes.c_int),
+                ("E", ctypes.c_double),
                 ("mu", ctypes.c_double), ("Ekin", ctypes.c_double), ("Epot", ctypes.c_double),
                 ("Eint", ctypes.c_double), ("residual", ctypes.c_double), ("virial", ctypes.c_double),
                 ("mass", ctypes.c_double)]
@@ -90,6 +93,9 @@ def load(path=LIB_PATH):
     lib.nlf_ground_state.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(GfOpts), vp, vp,
                                      ctypes.POINTER(GsStats)]
     lib.nlf_evolve.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(TsOpts), vp, dp]
+    lib.nlf_ground_state_batch.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(ctypes.POINTER(Phys)),
+                                           ctypes.POINTER(GfOpts), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(ctypes.POINTER(GsStats))]
     lib.nlf_plan_set_profiling.argtypes = [vp, ip]
     lib.nlf_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ip]
     for f in ["nlf_last_error", "nlf_strerror", "nlf_version"]:
@@ -229,12 +235,12 @@ class Plan:
         return arr
 
     def ground_state(self, beta, gamma, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
-                     cg_tol=0.0, cg_max_iter=0, psi0=None, V=None, out=None):
+                     cg_tol=0.0, cg_max_iter=0, psi0=None, V=None, out=None, mixed=False, eps_switch=0.0):
         """nlf_ground_state; returns (psi, [stats dict per field], status)."""
         phys = self._phys(beta, gamma, V)
         if V is not None:
             self._check_in(V, self.torch.float64, int(np.prod(self.n)))
-        gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter)
+        gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch)
         N = int(np.prod(self.n)) * self.batch
         if psi0 is not None:
             self._check_in(psi0, self.rdtype, N)
@@ -261,3 +267,25 @@ class Plan:
             dptr = diag.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         _check(load().nlf_evolve(self._h, phys, ctypes.byref(ts), _ptr(psi), dptr))
         return diag
+
+
+def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
+                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0):
+    """nlf_ground_state_batch over several plans (one per grid size); betas[i] / gammas[i] give
+    the per-field parameters of plan i.  Returns ([psi_i], [[stats]], status)."""
+    import torch
+    lib = load()
+    k = len(plans)
+    hs = (ctypes.c_void_p * k)(*[p._h.value for p in plans])
+    phys_keep = [p._phys(b, g, None) for p, b, g in zip(plans, betas, gammas)]
+    phys = (ctypes.POINTER(Phys) * k)(*[ctypes.cast(a, ctypes.POINTER(Phys)) for a in phys_keep])
+    outs = [torch.empty(p._shape(), dtype=p.rdtype, device="cuda") for p in plans]
+    psi = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+    psi0 = (ctypes.c_void_p * k)(*([None] * k))
+    st_keep = [(GsStats * p.batch)() for p in plans]
+    stats = (ctypes.POINTER(GsStats) * k)(*[ctypes.cast(a, ctypes.POINTER(GsStats)) for a in st_keep])
+    gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch)
+    status = lib.nlf_ground_state_batch(k, hs, phys, ctypes.byref(gf), psi0, psi, stats)
+    if status not in (OK, ENOCONV):
+        _check(status)
+    return outs, [[s.as_dict() for s in a] for a in st_keep], status

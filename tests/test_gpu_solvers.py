@@ -124,6 +124,41 @@ def test_gs_fp32_plan():
     assert abs(s32[0]["E"] - s64[0]["E"]) < 2e-6 * abs(s64[0]["E"])
 
 
+def test_gs_mixed_schedule_reaches_fp64_tolerance():
+    """FP32 bulk iterations, FP64 polish on the twin plan: the stopping rule eps0 = 1e-10 is met and
+    the energies equal those of a pure FP64 solve."""
+    n, L = (64, 64), (8.0, 8.0)
+    p64 = nlf.Plan(n, L, nlf.COULOMB2D)
+    _, s64, st64 = p64.ground_state(5.0, (1.0, 2.0), tau=0.5, eps0=1e-10)
+    p32 = nlf.Plan(n, L, nlf.COULOMB2D, prec=nlf.F32)
+    psi, s32, status = p32.ground_state(5.0, (1.0, 2.0), tau=0.5, eps0=1e-10, mixed=True)
+    assert status == nlf.OK and st64 == nlf.OK
+    s = s32[0]
+    assert s["iters_fp32"] > 0 and s["iters"] > s["iters_fp32"]
+    assert s["residual"] <= 1e-10
+    for key in ("E", "mu", "Ekin", "Epot", "Eint"):
+        assert abs(s[key] - s64[0][key]) < 1e-10 * max(1.0, abs(s64[0][key])), key
+    assert psi.dtype == torch.float32
+
+
+def test_gs_batch_over_plans_of_uneven_size():
+    """nlf_ground_state_batch: two grid sizes, two fields each, solved concurrently on separate
+    streams; every field equals its individual solve."""
+    sizes = [(64, 64), (128, 128)]
+    betas = [[3.0, 30.0], [10.0, 1.0]]
+    gams = [[(1.0, 1.0), (1.0, 1.5)], [(1.0, 0.7), (1.0, 1.2)]]
+    streams = [torch.cuda.Stream() for _ in sizes]
+    plans = [nlf.Plan(n, (16.0, 16.0), nlf.COULOMB2D, batch=2, stream=s.cuda_stream) for n, s in zip(sizes, streams)]
+    outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.5, eps0=1e-10)
+    assert status == nlf.OK
+    for i, n in enumerate(sizes):
+        for j in range(2):
+            single = nlf.Plan(n, (16.0, 16.0), nlf.COULOMB2D)
+            psi, st, _ = single.ground_state(betas[i][j], gams[i][j], tau=0.5, eps0=1e-10)
+            assert rel_err(outs[i][j].cpu().numpy(), psi.cpu().numpy()) < 1e-8
+            assert abs(stats[i][j]["E"] - st[0]["E"]) < 1e-10
+
+
 # ---- dynamics ---------------------------------------------------------------------------------
 
 def _psi0(n, L, seed=0):
