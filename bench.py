@@ -156,6 +156,37 @@ def load_traffic(kernel_stage):
     return None if v is None else float(v)
 
 
+def ground_states_per_s(torch, nlf, inputs):
+    """Second half of the metric: 64 batched 2D ground states (grids drawn from 64^2/128^2/256^2 on
+    [-16,16]^2, beta ~ U[10,1000], gamma ~ U[0.5,2], Coulomb 2D), gradient flow to
+    max|phi^{n+1}-phi^n|/tau <= 1e-10, FP32 bulk then FP64 polish, one plan and stream per size
+    class solved concurrently; timed once after an untimed warm-up solve of the same instances."""
+    inst = inputs.ground_state_batch_2d(seed=3, count=64)
+    groups = {}
+    for d in inst:
+        groups.setdefault(d["n"][0], []).append(d)
+    keys = sorted(groups)
+    streams = [torch.cuda.Stream() for _ in keys]
+    plans = [nlf.Plan((k, k), (16.0, 16.0), nlf.COULOMB2D, prec=nlf.F32, batch=len(groups[k]), stream=s.cuda_stream)
+             for k, s in zip(keys, streams)]
+    betas = [[d["beta"] for d in groups[k]] for k in keys]
+    gams = [[d["gamma"] for d in groups[k]] for k in keys]
+    kw = dict(tau=0.25, eps0=1e-10, max_iter=5000, mixed=True)
+    nlf.ground_state_batch(plans, betas, gams, **kw)          # warm-up (twin plans, workspaces)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stats, status = nlf.ground_state_batch(plans, betas, gams, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flat = [s for a in stats for s in a]
+    return {"value": len(inst) / dt, "unit": "ground states/s", "instances": len(inst),
+            "seconds": dt, "status": status, "tau": 0.25, "eps0": 1e-10, "schedule": "FP32 then FP64",
+            "max_residual": max(s["residual"] for s in flat),
+            "mean_outer_iters": float(np.mean([s["iters"] for s in flat])),
+            "mean_fp32_iters": float(np.mean([s["iters_fp32"] for s in flat])),
+            "sizes": {str(k): len(groups[k]) for k in keys}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", choices=["full", "prof"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ground-states", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -263,6 +295,7 @@ def main():
     }
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(n, L, rho)
+    gs = None if args.no_ground_states else ground_states_per_s(torch, nlf, inputs)
 
     value = 2 * args.steps / t64
     out = {
@@ -286,6 +319,7 @@ def main():
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage_avg.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "ground_states": gs,
     }
     print(json.dumps(out))
 

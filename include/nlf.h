@@ -168,7 +168,7 @@ typedef struct {
 } nlf_gf_opts;
 
 typedef struct {
-    int    iters;           /* outer gradient-flow steps taken (all precisions)             */
+    int    iters;           /* outer gradient-flow steps this field took (all precisions)   */
     int    iters_fp32;      /* of which in FP32 (mixed schedule)                            */
     int    cg_iters;        /* inner linear-solver iterations, summed                       */
     double E, mu, Ekin, Epot, Eint;
@@ -211,6 +211,45 @@ typedef struct {
 
 int nlf_evolve(nlf_plan* plan, const nlf_phys* phys, const nlf_ts_opts* ts, void* psi_dev,
                double* diag_host);
+
+/* ---- learned warm start (project addition, not in the paper) ----------------------------------
+ * A small FP32 MLP, x (n_in) -> tanh(W1 x + b1) (H) -> tanh(W2 . + b2) (H) -> W3 . + b3 (n_out),
+ * whose inputs are standardised by (x - mean) / stdv.  For the warm start the inputs are
+ * (ln beta, gamma_0, .., gamma_{d-1}) of a field and the outputs its ground state on a coarse
+ * grid of coarse_n^d points of the same box.  All device arrays are FP32 and row-major; the
+ * parameter vector is W1 [n_in][H], b1 [H], W2 [H][H], b2 [H], W3 [H][n_out], b3 [n_out].
+ * The model owns its device buffers; calls run on its stream.                                 */
+typedef struct nlf_model nlf_model;
+int nlf_ws_create(int n_in, int n_hidden, int n_out, unsigned long long seed, void* stream,
+                  nlf_model** out);      /* Glorot-uniform weights from seed, zero biases       */
+int nlf_ws_destroy(nlf_model* model);
+int nlf_ws_num_params(const nlf_model* model, long long* count);
+/* copy the parameters out to / in from host memory (either pointer may be NULL)                */
+int nlf_ws_params(nlf_model* model, float* host_out, const float* host_in);
+int nlf_ws_set_standardisation(nlf_model* model, const float* mean_host, const float* stdv_host);
+/* y_dev [batch][n_out] = network(x_dev [batch][n_in])                                           */
+int nlf_ws_forward(nlf_model* model, int batch, const float* x_dev, float* y_dev);
+/* mean-squared-error loss of one batch against t_dev [batch][n_out] and its gradient with respect
+ * to the parameters (grad_dev: n_params floats, or NULL); loss_host may be NULL               */
+int nlf_ws_loss_grad(nlf_model* model, int batch, const float* x_dev, const float* t_dev, float* grad_dev,
+                     double* loss_host);
+/* Adam (b1 0.9, b2 0.999, eps 1e-8) over `epochs` passes of minibatches of the n samples;
+ * loss_host (epochs entries, or NULL) receives the mean minibatch loss of each epoch           */
+int nlf_ws_train(nlf_model* model, int n, const float* x_dev, const float* t_dev, int epochs, int minibatch,
+                 double lr, double* loss_host);
+/* Initial guesses for the plan's fields from their parameters (phys: batch entries, beta > 0):
+ * network output on the coarse grid (coarse_n even, <= 1024), resampled to the plan grid by
+ * band-limited (periodic Dirichlet-kernel) interpolation along each axis in FP64, absolute value;
+ * psi0_dev [batch][n] in the plan precision (nlf_ground_state normalises it).                  */
+int nlf_ws_predict(nlf_model* model, nlf_plan* plan, const nlf_phys* phys, int coarse_n, void* psi0_dev);
+
+/* Warm-started ground states: the network's guess (nlf_ws_predict) and the harmonic-oscillator
+ * Gaussian each take one gradient-flow step; per field the start with the smaller residual
+ * max|phi^1 - phi^0|/tau is kept (the Gaussian is the fallback), then nlf_ground_state runs from
+ * it.  used_host (batch ints, or NULL) receives 1 where the network's guess was kept.  The two
+ * judging steps are included in stats[].iters.                                                */
+int nlf_ws_ground_state(nlf_model* model, int coarse_n, nlf_plan* plan, const nlf_phys* phys,
+                        const nlf_gf_opts* gf, void* psi_dev, nlf_gs_stats* stats, int* used_host);
 
 /* Message for the calling thread's last error ("" if none).                                 */
 const char* nlf_last_error(void);

@@ -144,6 +144,9 @@ int spread(nlf_plan* p);                                      // cbuf -> grid_b
 int fold_c(nlf_plan* p, const void* c);                       // canonical full c -> cbuf (sorted, folded)
 int potential(nlf_plan* p, const void* rho, void* u);
 
+// harmonic-oscillator Gaussian initial guesses of the plan's fields (unnormalised), solvers.hip
+int ho_guess(nlf_plan* p, const nlf_phys* phys, void* out);
+
 // stage timing: returns an opaque mark index (or -1 when profiling is off)
 int stage_begin(nlf_plan* p);
 int stage_end(nlf_plan* p, int stage, int mark);

@@ -130,7 +130,7 @@ struct Fld {
     double cgtol;                // inner relative tolerance of the current solve
     double cgtol_min;            // the caller's (final) inner tolerance
     int cg_last;                 // iterations of the current solve
-    int pad2;
+    int done_at;                 // outer step at which the field retired
     int conv;                    // PCG converged
     int done;                    // outer flow converged (field retired)
     int cg_iters;
@@ -207,14 +207,17 @@ __global__ void k_normalize(Geo g, Fld* fl, const T* v, T* phi, T* rho, const do
 // only needs to be accurate relative to the size of the step it computes, so its tolerance
 // follows the residual down to the caller's tolerance: max(cg_tol, min(1e-3, 1e-3 tau res)).
 template <typename T>
-__global__ void k_residual_final(Fld* fl, const double* part_r, int nblk, double eps0) {
+__global__ void k_residual_final(Fld* fl, const double* part_r, int nblk, double eps0, int step) {
     const int b = blockIdx.x;
     if (fl[b].done) return;
     double r = max_parts(part_r + b * MAXBLK, nblk);
     if (threadIdx.x == 0) {
         fl[b].res = r;
         if (!(r == r) || r > 1e300) fl[b].nonfinite = 1;
-        if (r <= eps0) fl[b].done = 1;
+        if (r <= eps0) {
+            fl[b].done = 1;
+            fl[b].done_at = step;
+        }
         fl[b].cgtol = fmax(fl[b].cgtol_min, fmin(1e-3, 1e-3 * fl[b].tau * r));
     }
 }
@@ -745,7 +748,7 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
         hipLaunchKernelGGL((k_norm2_part<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, part_n);
         hipLaunchKernelGGL((k_normalize<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, (T*)w.phi,
                            (T*)w.rho, part_n, part_r, nb, 1);
-        hipLaunchKernelGGL((k_residual_final<T>), dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_r, nb, eps0);
+        hipLaunchKernelGGL((k_residual_final<T>), dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_r, nb, eps0, it);
         NLF_HIP(hipGetLastError());
         if (it % check_every == 0 || it == max_iter) {
             NLF_TRY(read_flds(p, w, fh));
@@ -761,6 +764,7 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
                         stall[b] = 0;
                     } else if (++stall[b] >= 3) {
                         fh[b].done = 1;
+                        fh[b].done_at = it;
                         stalled[b] = 1;
                         retire = true;
                     }
@@ -777,7 +781,7 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
     bool all = true;
     for (int b = 0; b < B; ++b) {
         nlf_gs_stats& st = stats[b];
-        st.iters = it - 1;
+        st.iters = fh[b].done ? fh[b].done_at : it - 1;
         st.iters_fp32 = (sizeof(T) == 4) ? st.iters : 0;
         st.cg_iters = fh[b].cg_iters;
         st.Ekin = e[b * 4 + 0];
@@ -865,6 +869,25 @@ static int evolve_t(nlf_plan* p, const nlf_phys* phys, const nlf_ts_opts* ts, vo
         if (de && diag && s % de == 0) NLF_TRY(record(slot++));
     }
     NLF_TRY(flush_kin());
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    return NLF_OK;
+}
+
+int ho_guess(nlf_plan* p, const nlf_phys* phys, void* out) {
+    SolverWs* wp;
+    NLF_TRY(solver_ws(p, &wp));
+    const int B = p->batch;
+    std::vector<Fld> fh(B);
+    for (int b = 0; b < B; ++b) {
+        std::memset(&fh[b], 0, sizeof(Fld));
+        for (int a = 0; a < 3; ++a) fh[b].g2[a] = (a < p->dim) ? phys[b].gamma[a] * phys[b].gamma[a] : 0.0;
+    }
+    NLF_HIP(hipMemcpyAsync(wp->fl, fh.data(), B * sizeof(Fld), hipMemcpyHostToDevice, p->stream));
+    const Geo g = geo_of(p);
+    dim3 grid(nblocks(p), B);
+    if (p->prec == NLF_F64) hipLaunchKernelGGL((k_ho_init<double>), grid, dim3(RB_T), 0, p->stream, g, wp->fl, (double*)out);
+    else hipLaunchKernelGGL((k_ho_init<float>), grid, dim3(RB_T), 0, p->stream, g, wp->fl, (float*)out);
+    NLF_HIP(hipGetLastError());
     NLF_HIP(hipStreamSynchronize(p->stream));
     return NLF_OK;
 }

@@ -111,3 +111,14 @@ def warmstart_instances_3d(seed, count):
         g = rng.uniform(0.5, 2.0, size=3)
         out.append(dict(beta=beta, gamma=tuple(float(v) for v in g)))
     return out
+
+
+def warmstart_instances_2d(seed, count, beta_lo=1.0, beta_hi=50.0):
+    """2D warm-start instances: beta log-uniform in [beta_lo, beta_hi], (gx, gy) ~ U[0.5,2]^2, in this order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        beta = float(np.exp(rng.uniform(np.log(beta_lo), np.log(beta_hi))))
+        g = rng.uniform(0.5, 2.0, size=2)
+        out.append(dict(beta=beta, gamma=tuple(float(v) for v in g)))
+    return out

@@ -20,7 +20,9 @@ EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan
            "nlf_potential", "nlf_type2", "nlf_type1", "nlf_ground_state", "nlf_ground_state_batch",
            "nlf_evolve",
            "nlf_last_error", "nlf_strerror", "nlf_version", "nlf_plan_set_profiling",
-           "nlf_plan_stage_times"]
+           "nlf_plan_stage_times", "nlf_ws_create", "nlf_ws_destroy", "nlf_ws_num_params", "nlf_ws_params",
+           "nlf_ws_set_standardisation", "nlf_ws_forward", "nlf_ws_loss_grad", "nlf_ws_train",
+           "nlf_ws_predict", "nlf_ws_ground_state"]
 STAGES = ["moments", "fft_fwd", "interp", "zero", "spread", "fft_inv"]
 
 
@@ -98,6 +100,18 @@ def load(path=LIB_PATH):
                                            ctypes.POINTER(ctypes.POINTER(GsStats))]
     lib.nlf_plan_set_profiling.argtypes = [vp, ip]
     lib.nlf_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ip]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.nlf_ws_create.argtypes = [ip, ip, ip, ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
+    lib.nlf_ws_destroy.argtypes = [vp]
+    lib.nlf_ws_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.nlf_ws_params.argtypes = [vp, fp, fp]
+    lib.nlf_ws_set_standardisation.argtypes = [vp, fp, fp]
+    lib.nlf_ws_forward.argtypes = [vp, ip, vp, vp]
+    lib.nlf_ws_loss_grad.argtypes = [vp, ip, vp, vp, vp, dp]
+    lib.nlf_ws_train.argtypes = [vp, ip, vp, vp, ip, ip, ctypes.c_double, dp]
+    lib.nlf_ws_predict.argtypes = [vp, vp, ctypes.POINTER(Phys), ip, vp]
+    lib.nlf_ws_ground_state.argtypes = [vp, ip, vp, ctypes.POINTER(Phys), ctypes.POINTER(GfOpts), vp,
+                                        ctypes.POINTER(GsStats), ctypes.POINTER(ctypes.c_int)]
     for f in ["nlf_last_error", "nlf_strerror", "nlf_version"]:
         getattr(lib, f).restype = ctypes.c_char_p
     lib.nlf_strerror.argtypes = [ip]
@@ -289,3 +303,87 @@ def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=1000
     if status not in (OK, ENOCONV):
         _check(status)
     return outs, [[s.as_dict() for s in a] for a in st_keep], status
+
+
+class Model:
+    """The warm-start MLP (nlf_ws_*): n_in -> H (tanh) -> H (tanh) -> n_out, FP32 on the device."""
+
+    def __init__(self, n_in, hidden, n_out, seed=0, stream=None):
+        import torch
+        self.torch = torch
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.nlf_ws_create(int(n_in), int(hidden), int(n_out), int(seed), ctypes.c_void_p(stream),
+                                 ctypes.byref(h)))
+        self._h = h
+        self.n_in, self.hidden, self.n_out = n_in, hidden, n_out
+        c = ctypes.c_longlong()
+        _check(lib.nlf_ws_num_params(h, ctypes.byref(c)))
+        self.n_params = c.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().nlf_ws_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(load().nlf_ws_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), None))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(load().nlf_ws_params(self._h, None, theta.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def set_standardisation(self, mean, stdv):
+        m = np.zeros(8, dtype=np.float32)
+        sd = np.ones(8, dtype=np.float32)
+        m[:self.n_in] = mean
+        sd[:self.n_in] = stdv
+        _check(load().nlf_ws_set_standardisation(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                 sd.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def forward(self, x):
+        B = x.shape[0]
+        y = self.torch.empty((B, self.n_out), dtype=self.torch.float32, device=x.device)
+        _check(load().nlf_ws_forward(self._h, B, _ptr(x), _ptr(y)))
+        return y
+
+    def loss_grad(self, x, t):
+        g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=x.device)
+        loss = ctypes.c_double()
+        _check(load().nlf_ws_loss_grad(self._h, x.shape[0], _ptr(x), _ptr(t), _ptr(g), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train(self, x, t, epochs, minibatch=0, lr=1e-3):
+        hist = np.zeros(max(epochs, 1))
+        _check(load().nlf_ws_train(self._h, x.shape[0], _ptr(x), _ptr(t), int(epochs), int(minibatch),
+                                   float(lr), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return hist[:epochs]
+
+    def predict(self, plan, betas, gammas, coarse_n):
+        phys = plan._phys(betas, gammas, None)
+        out = self.torch.empty(plan._shape(), dtype=plan.rdtype, device="cuda")
+        _check(load().nlf_ws_predict(self._h, plan._h, phys, int(coarse_n), _ptr(out)))
+        return out
+
+    def ground_state(self, plan, betas, gammas, coarse_n, tau=1e-2, eps0=1e-10, max_iter=100000,
+                     check_every=10, cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0):
+        """nlf_ws_ground_state; returns (psi, [stats], status, used flags)."""
+        phys = plan._phys(betas, gammas, None)
+        gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch)
+        out = self.torch.empty(plan._shape(), dtype=plan.rdtype, device="cuda")
+        stats = (GsStats * plan.batch)()
+        used = (ctypes.c_int * plan.batch)()
+        st = load().nlf_ws_ground_state(self._h, int(coarse_n), plan._h, phys, ctypes.byref(gf), _ptr(out), stats, used)
+        if st not in (OK, ENOCONV):
+            _check(st)
+        return out, [s.as_dict() for s in stats], st, list(used)

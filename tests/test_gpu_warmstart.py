@@ -1,0 +1,91 @@
+"""GPU warm-start network (libnlf.so nlf_ws_*): gradients against the FP64 oracle, training,
+exact band-limited resampling, and the iterations the learned start saves."""
+import numpy as np
+import pytest
+
+from oracle import warmstart as ows
+from paper_1410_3584_amd import inputs
+from gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_1410_3584_amd import nlf, warmstart  # noqa: E402
+
+
+def test_gradient_matches_oracle():
+    n_in, H, n_out, B = 3, 9, 11, 7
+    m = nlf.Model(n_in, H, n_out, seed=3)
+    rng = np.random.default_rng(1)
+    theta = rng.normal(scale=0.4, size=m.n_params).astype(np.float32)
+    m.set_params(theta)
+    mean, stdv = np.array([0.5, -0.2, 1.0]), np.array([1.5, 0.7, 2.0])
+    m.set_standardisation(mean, stdv)
+    x = rng.normal(size=(B, n_in)).astype(np.float32)
+    t = rng.normal(size=(B, n_out)).astype(np.float32)
+    loss, g = m.loss_grad(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"))
+    lo, go = ows.loss_grad(theta.astype(np.float64), x, t, n_in, H, n_out,
+                           mean.astype(np.float32), stdv.astype(np.float32))
+    assert abs(loss - lo) < 1e-5 * abs(lo)
+    assert np.max(np.abs(g.cpu().numpy() - go)) < 1e-5 * np.max(np.abs(go))
+    y = m.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    yo = ows.forward(theta.astype(np.float64), x, n_in, H, n_out, mean.astype(np.float32), stdv.astype(np.float32))[3]
+    assert rel_err(y, yo) < 1e-5
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, size=(256, 3)).astype(np.float32)
+    t = np.stack([np.sin(x[:, 0] + x[:, 1]), x[:, 2] ** 2, np.cos(2 * x[:, 0])], 1).astype(np.float32)
+    m = nlf.Model(3, 32, 3, seed=0)
+    m.set_standardisation(x.mean(0), x.std(0))
+    hist = m.train(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"), 400, minibatch=64, lr=3e-3)
+    assert hist[-1] < 0.05 * hist[0]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_resampling_is_band_limited_interpolation(dim):
+    """With W3 = 0 the network outputs its bias b3; nlf_ws_predict must return the trigonometric
+    interpolant of that coarse field (numpy: FFT zero-padding with the Nyquist mode split)."""
+    nc, nf = 8, 16
+    m = nlf.Model(1 + dim, 4, nc ** dim, seed=0)
+    theta = np.zeros(m.n_params, dtype=np.float32)
+    X = np.meshgrid(*[np.arange(nc) * (2 * np.pi / nc)] * dim, indexing="ij")
+    field = 1.0 + 0.3 * np.cos(X[0]) + 0.2 * np.sin(2 * X[-1]) + 0.1 * np.cos(X[0] + 3 * X[-1])
+    theta[-nc ** dim:] = field.reshape(-1)
+    m.set_params(theta)
+    plan = nlf.Plan((nf,) * dim, (4.0,) * dim, nlf.COULOMB3D if dim == 3 else nlf.COULOMB2D)
+    got = m.predict(plan, [2.0], [(1.0,) * dim], nc).cpu().numpy()
+    F = np.fft.fftn(field.astype(np.float32).astype(np.float64))
+    G = np.zeros((nf,) * dim, dtype=complex)
+    k = np.fft.fftfreq(nc, 1.0 / nc).astype(int)
+    for idx in np.ndindex(*F.shape):
+        kk = [k[i] for i in idx]
+        # split the Nyquist mode half/half between +nc/2 and -nc/2
+        targets = [[]]
+        wts = [1.0]
+        for kv in kk:
+            opts = [kv, -kv] if abs(kv) == nc // 2 else [kv]
+            targets = [t + [o] for t in targets for o in opts]
+            wts = [w * (0.5 if len(opts) == 2 else 1.0) for w in wts for _ in opts]
+        for tg, w in zip(targets, wts):
+            G[tuple(v % nf for v in tg)] += w * F[idx]
+    want = np.real(np.fft.ifftn(G)) * (nf / nc) ** dim
+    assert np.max(np.abs(got - np.abs(want))) < 1e-6 * np.max(np.abs(want))
+
+
+def test_learned_start_saves_iterations_2d():
+    """Small end-to-end run: targets from the library's own solver on a 16^2 grid of [-8,8]^2,
+    96 training instances, 12 held out solved on 64^2 to eps0 = 1e-10 from both starts."""
+    tr = inputs.warmstart_instances_2d(0, 96)
+    te = inputs.warmstart_instances_2d(1, 12)
+    T = warmstart.solve_targets(tr, 16, 8.0, nlf.COULOMB2D, 2, batch=96)
+    X = torch.tensor(warmstart.features([d["beta"] for d in tr], [d["gamma"] for d in tr]), device="cuda")
+    model, hist = warmstart.train_model(X, T, hidden=64, epochs=1500, lr=3e-3)
+    assert hist[-1] < 1e-2 * hist[0]
+    r = warmstart.compare(model, te, 64, 8.0, nlf.COULOMB2D, 2, 16, tau=0.5)
+    print(r, flush=True)
+    assert r["status_gauss"] == nlf.OK and r["status_learned"] == nlf.OK
+    assert r["used_learned"] >= 1
+    assert r["iters_learned_batch"] < r["iters_gauss_batch"]
+    assert r["max_energy_difference"] < 1e-9
