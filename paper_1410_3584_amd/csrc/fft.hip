@@ -28,11 +28,14 @@ template <typename T> __device__ __forceinline__ V2<T> cmul(V2<T> a, V2<T> b) {
     return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Elements held in LDS per workgroup (128 KiB in both precisions) and threads per workgroup:
-// every thread owns 4 radix-4 (or 8 radix-2) butterflies per pass.
+// Elements held in LDS per workgroup and threads per workgroup.  The strided-axis kernel keeps
+// C adjacent columns (128 KiB in both precisions) so that row segments load contiguously; the
+// contiguous-axis kernel needs no such block and keeps at most 2048 elements (one or two long
+// lines), which gives many small workgroups per CU.
 template <typename T> struct FftCfg;
 template <> struct FftCfg<double> { static constexpr int E = 8192, NT = 512; };
 template <> struct FftCfg<float>  { static constexpr int E = 16384, NT = 1024; };
+struct RowCfg { static constexpr int E = 2048, NT = 256; };
 
 // data index j (0..nd-1, x_j = -L + j h) -> row of the 2x oversampled periodic grid holding
 // centred frequency/position j - nd/2
@@ -44,10 +47,9 @@ __device__ __forceinline__ bool is_data_row(int r, int nd, int Mr) { return r < 
 
 // In-place multi-line Stockham FFT of nl lines of length n = 2^lg held in buf[line*pitch + i].
 // tw[t] = exp(-2 pi i t / n).  DIR = -1 forward, +1 inverse (unnormalised).
-template <typename T, int DIR>
+template <typename T, int DIR, int NT, int E>
 __device__ void lds_fft(V2<T>* buf, int pitch, int n, int lg, int nl, const V2<T>* __restrict__ tw) {
-    constexpr int NT = FftCfg<T>::NT;
-    constexpr int RB = FftCfg<T>::E / (4 * NT);   // radix-4 butterflies per thread
+    constexpr int RB = E / (4 * NT);   // radix-4 butterflies per thread
     const int tid = threadIdx.x;
     int p = 1;
     if (lg & 1) {
@@ -157,10 +159,10 @@ struct RowsArgs {
 };
 
 template <typename T, typename TIO, int DIR, int LOAD, int STORE>
-__global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
+__global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    constexpr int NT = FftCfg<T>::NT;
+    constexpr int NT = RowCfg::NT;
     const int n = a.n;
     const int pitch = n;
     const int b = blockIdx.y;
@@ -214,7 +216,7 @@ __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_rows(RowsArgs a) {
         }
     }
     __syncthreads();
-    lds_fft<T, DIR>(buf, pitch, n, a.lg, nl, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, RowCfg::E>(buf, pitch, n, a.lg, nl, reinterpret_cast<const V2<T>*>(a.tw));
 
     // ---- store
     if (STORE == STORE_GRID) {
@@ -291,7 +293,7 @@ __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_cols(ColsArgs a) {
         buf[c * pitch + r] = v;
     }
     __syncthreads();
-    lds_fft<T, DIR>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, FftCfg<T>::E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
         if (!SPRUNE || is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
@@ -314,7 +316,7 @@ static int ilog2(int v) {
 
 template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
 static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
-    constexpr int E = FftCfg<T>::E, NT = FftCfg<T>::NT;
+    constexpr int E = RowCfg::E, NT = RowCfg::NT;
     a.lg = ilog2(a.n);
     a.lines_per_wg = std::max(1, E / a.n);
     if (a.n > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);

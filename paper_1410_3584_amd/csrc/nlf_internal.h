@@ -43,15 +43,15 @@ struct Chunk {
 constexpr int kChunk = 128;   // threads per interpolation/spreading workgroup = nodes per chunk
 constexpr int kMaxMsp = 16;
 
-// A gather-spread work item: up to kGChunk candidate nodes of one output tile of the oversampled
-// grid (gather tiles are 8x8 in 2D and 4x4x4 in 3D: 64 cells).
+// A tile-gather work item: up to kMItem candidate nodes of one gather tile of the oversampled
+// grid (8 x 16 cells in 2D, 8 x 4 x 4 in 3D: 128 cells), taken kMChunk at a time.
 struct GItem {
     int g0, g1, g2;    // tile coordinates
     int count;         // candidates in this item
     long long start;   // first entry in the candidate list
 };
-constexpr int kGChunk = 256;
-constexpr int kGCells = 64;
+constexpr int kMChunk = 128;
+constexpr int kMItem = 8 * kMChunk;
 
 // Gaussian-gridding constants handed to the kernels by value.
 struct GaussConst {
@@ -95,6 +95,7 @@ struct nlf_plan {
     int* gcand = nullptr;
     nlf::GItem* gitems = nullptr;
     int ngitems = 0;
+    double* iacc = nullptr;     // [batch][Mh] complex FP64: tile-gathered interpolation sums
     double* dec[3] = {nullptr, nullptr, nullptr};   // 1 / c_g(j - n/2), length n_i
     void* tw_big[3] = {nullptr, nullptr, nullptr};  // twiddles of length Mr_i (plan precision)
     void* tw_small[3] = {nullptr, nullptr, nullptr};// twiddles of length n_i (solver FFTs)

@@ -2,14 +2,18 @@
 //
 // Gaussian gridding with oversampling 2: a node at position s (in oversampled cells) couples to
 // the 2*msp cells l0+p, p = -msp+1..msp, l0 = floor(s), with the separable weight
-// prod_i exp(-alpha (p_i - delta_i)^2), delta_i = s_i - l0_i.  Nodes are pre-sorted into bins
-// (tiles of the oversampled grid) and cut into chunks of <= kChunk nodes; one workgroup handles
-// one chunk, one thread one node.
-//   interpolation (type-2): the chunk's grid window is staged in LDS (a whole 2D window, or in 3D
-//     one axis-0 plane at a time), each thread gathers its stencil from LDS; the epilogue applies
-//     the kernel symbol and quadrature weight in FP64 (the symbol_weight step, fused).
-//   spreading (type-1): each thread adds its stencil into the LDS window with LDS atomics; the
-//     window is then added to the global grid with one global atomic per window cell.
+// prod_i exp(-alpha (p_i - delta_i)^2), delta_i = s_i - l0_i.
+//
+// Main path (tile-gathered, FP64 matrix cores).  The oversampled grid is cut into gather tiles of
+// 8 x 16 cells (2D) or 8 x 4 x 4 cells (3D); the plan lists, per tile, the nodes whose stencil
+// overlaps it, in items of <= kMChunk nodes.  For one item both directions are dense products:
+//   spreading (type-1):      F = A^T B, A[k][(comp, x)] = c_k w0_k[x], B[k][j] = tile weights
+//   interpolation (type-2):  H = G B,   then u_k = sum_x w0_k[x] H[x][k]
+// computed with v_mfma_f64_16x16x4 from weights staged in LDS; tiles receive their sums with
+// one atomic per cell component, nodes with one per component and tile.  The symbol/weight
+// multiply (the symbol_weight step) is the per-node epilogue of the interpolation, in FP64.
+// Fallback (candidate list too large): node-parallel kernels over binned chunks, the grid window
+// staged in LDS (interpolation) or LDS atomics (spreading).
 // Only half of the node set is evaluated: rho is real, so rhohat(-k) = conj(rhohat(k)), and the
 // node set is symmetric under k -> -k (even n_phi, symmetric Gauss-Legendre in cos theta).
 #include <algorithm>
@@ -23,10 +27,10 @@ template <typename T> __device__ __forceinline__ V2<T> mk2(T x, T y);
 template <> __device__ __forceinline__ float2 mk2<float>(float x, float y) { return make_float2(x, y); }
 template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) { return make_double2(x, y); }
 
-__device__ __forceinline__ int wrap(int v, int M) {
-    v %= M;
-    return v < 0 ? v + M : v;
-}
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// index modulo an oversampled grid extent (always a power of two)
+__device__ __forceinline__ int wrap(int v, int M) { return v & (M - 1); }
 
 // Separable Gaussian weights for one axis: w[q] = exp(-alpha (q - msp + 1 - delta)^2), computed as
 // exp(-alpha delta^2) * exp(2 alpha delta)^p * exp(-alpha p^2) (Greengard-Lee fast gridding).
@@ -416,122 +420,233 @@ __device__ __forceinline__ void tile_weights(double s, int o, int Mr, double alp
     }
 }
 
-template <typename T, typename TG, int MSP>
-__global__ void __launch_bounds__(kGChunk) k_gspread2(V2<TG>* __restrict__ grid, long long gstride,
-                                                     const V2<T>* __restrict__ cbuf, long long cstride,
-                                                     NodeArgs na, const GItem* __restrict__ items, int nitems,
-                                                     const int* __restrict__ cand, double qq) {
-    constexpr int GT = 8;
-    // staged weights and partial sums are FP64 in both precisions: the FP32 path stores its
-    // grids and node values in FP32 but accumulates each cell's sum in FP64 registers (same issue
-    // rate as non-packed FP32 on gfx950)
-    __shared__ double2 A[kGChunk][GT];
-    __shared__ double Bw[kGChunk][GT];
-    __shared__ double2 part[kGChunk / 64][64];
+// The sum a gather tile receives from a block of K candidate nodes,
+//   F[x][y] = sum_k c_k w0_k[x] w1_k[y]            (2D tile: 8 x 16 cells)
+//   F[x][(y,z)] = sum_k c_k w0_k[x] w1_k[y] w2_k[z]  (3D tile: 8 x 4 x 4 cells),
+// is the product A^T B of the K x 16 matrices A[k][(comp, x)] = (Re|Im c_k) w0_k[x] and
+// B[k][j] = w1_k[y] (2D) or w1_k[y] w2_k[z] (3D, j = 4y + z): a dense contraction over the
+// candidates, run on the FP64 matrix cores, 4 candidates per v_mfma_f64_16x16x4.
+//
+// Phase 1: thread t < K builds row t of A, thread K + t row t of B (rows past the item's count are
+// zero), in LDS rows of 16 doubles whose 16-byte chunks are XOR-swizzled by the row index so that
+// the per-thread row stores hit distinct banks.  Phase 2: wave w multiplies candidates
+// [w K/4, (w+1) K/4).  Phase 3: the four partial 16 x 16 tiles are summed through LDS and added
+// to the grid with one FP64 (or FP32) atomic per cell component.
+__device__ __forceinline__ int mrow_slot(int k, int chunk) {
+    return ((chunk ^ ((k >> 1) & 7) ^ ((k & 1) << 2)) & 7);
+}
+
+template <typename T, typename TG, int MSP, int DIM>
+__global__ void __launch_bounds__(2 * kMChunk) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
+                                                        const V2<T>* __restrict__ cbuf, long long cstride,
+                                                        NodeArgs na, const GItem* __restrict__ items, int nitems,
+                                                        const int* __restrict__ cand, double qq) {
+    static_assert(kMChunk % 16 == 0, "four waves, whole MFMA steps each");
+    __shared__ __align__(16) double S[2 * kMChunk * 16];
     const int iid = chunk_id(nitems);
     if (iid >= nitems) return;
     const GItem it = items[iid];
     const int b = blockIdx.y;
     const int t = threadIdx.x;
-    const int o0 = it.g0 * GT, o1 = it.g1 * GT;
-    if (t < it.count) {
-        const int node = cand[it.start + t];
-        double w0[GT], w1[GT];
-        tile_weights<MSP, GT>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
-        tile_weights<MSP, GT>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
-        const V2<T> c = cbuf[(long long)b * cstride + node];
-#pragma unroll
-        for (int k = 0; k < GT; ++k) {
-            A[t][k] = make_double2((double)c.x * w0[k], (double)c.y * w0[k]);
-            Bw[t][k] = w1[k];
-        }
-    }
-    __syncthreads();
+    const int o0 = it.g0 * 8;
+    const int o1 = it.g1 * (DIM == 2 ? 16 : 4);
+    const int o2 = it.g2 * 4;
+    const int k = t & (kMChunk - 1);
+    const bool is_a = t < kMChunk;
     const int wv = t >> 6, lane = t & 63;
-    const int ix = lane >> 3, iy = lane & 7;
-    const int m0 = wv * 64, m1 = min(it.count, m0 + 64);
-    double ax = 0, ay = 0;
-    for (int m = m0; m < m1; ++m) {
-        const double2 a = A[m][ix];
-        const double bw = Bw[m][iy];
-        ax += a.x * bw;
-        ay += a.y * bw;
-    }
-    part[wv][lane] = make_double2(ax, ay);
-    __syncthreads();
-    if (t < 64) {
-        double sx = 0, sy = 0;
+    const int r = lane & 15;
+    const int kb = wv * (kMChunk / 4);
+    d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    for (int base = 0; base < it.count; base += kMChunk) {
+        const int cnt = min(kMChunk, it.count - base);
+        if (base > 0) __syncthreads();   // the previous block's products have read S
+        double row[16];
 #pragma unroll
-        for (int q = 0; q < kGChunk / 64; ++q) {
-            sx += part[q][t].x;
-            sy += part[q][t].y;
+        for (int j = 0; j < 16; ++j) row[j] = 0.0;
+        if (k < cnt) {
+            const int node = cand[it.start + base + k];
+            if (is_a) {
+                double w0[8];
+                tile_weights<MSP, 8>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
+                const V2<T> c = cbuf[(long long)b * cstride + node];
+                const double cx = (double)c.x, cy = (double)c.y;
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    row[x] = cx * w0[x];
+                    row[8 + x] = cy * w0[x];
+                }
+            } else if (DIM == 2) {
+                tile_weights<MSP, 16>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, row);
+            } else {
+                double w1[4], w2[4];
+                tile_weights<MSP, 4>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
+                tile_weights<MSP, 4>(na.s[2][node], o2, na.Mr[2], na.gc.alpha, qq, w2);
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) row[4 * y + z] = w1[y] * w2[z];
+            }
         }
-        if (sx != 0.0 || sy != 0.0) {
-            const int cx = o0 + (t >> 3), cy = o1 + (t & 7);
-            TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride + (long long)cx * na.Mr[1] + cy);
-            global_add<TG>(dst, (TG)sx);
-            global_add<TG>(dst + 1, (TG)sy);
+        double* mine = S + (is_a ? 0 : kMChunk * 16) + k * 16;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            *reinterpret_cast<double2*>(mine + 2 * mrow_slot(k, c)) = make_double2(row[2 * c], row[2 * c + 1]);
+        __syncthreads();
+        if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
+            constexpr int kSteps = kMChunk / 16;
+            double av[kSteps], bv[kSteps];
+#pragma unroll
+            for (int q = 0; q < kSteps; ++q) {
+                const int kk = kb + 4 * q + (lane >> 4);
+                const int off = kk * 16 + 2 * mrow_slot(kk, r >> 1) + (r & 1);
+                av[q] = S[off];
+                bv[q] = S[kMChunk * 16 + off];
+            }
+#pragma unroll
+            for (int q = 0; q < kSteps; q += 2) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 1], bv[q + 1], acc1, 0, 0, 0);
+            }
+        }
+    }
+    const d4_t acc = acc0 + acc1;
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[(wv * 4 + v) * 64 + lane] = acc[v];
+    __syncthreads();
+    {
+        // v_mfma_f64_16x16x4 leaves element (i, j) of the 16 x 16 product in register v = i / 4 of
+        // lane l = 16 (i mod 4) + j
+        const int v = t >> 6, l = t & 63;
+        const double sum = S[(0 * 4 + v) * 64 + l] + S[(1 * 4 + v) * 64 + l] + S[(2 * 4 + v) * 64 + l] +
+                           S[(3 * 4 + v) * 64 + l];
+        const int i = 4 * v + (l >> 4), j = l & 15;
+        if (sum != 0.0) {
+            const int x = o0 + (i & 7);
+            long long cell;
+            if (DIM == 2)
+                cell = (long long)x * na.Mr[1] + o1 + j;
+            else
+                cell = ((long long)x * na.Mr[1] + o1 + (j >> 2)) * na.Mr[2] + o2 + (j & 3);
+            TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride + cell) + (i >> 3);
+            global_add<TG>(dst, (TG)sum);
         }
     }
 }
 
-template <typename T, typename TG, int MSP>
-__global__ void __launch_bounds__(kGChunk) k_gspread3(V2<TG>* __restrict__ grid, long long gstride,
-                                                     const V2<T>* __restrict__ cbuf, long long cstride,
-                                                     NodeArgs na, const GItem* __restrict__ items, int nitems,
-                                                     const int* __restrict__ cand, double qq) {
-    constexpr int GT = 4;
-    __shared__ double2 A[kGChunk][GT];
-    __shared__ double Bw[kGChunk][GT];
-    __shared__ double Cw[kGChunk][GT];
-    __shared__ double2 part[kGChunk / 64][64];
+// ---- tile-gathered interpolation on the FP64 matrix cores -----------------------------------------
+// For one gather tile with grid values G and a block of candidate nodes k, the part of the
+// interpolation sum that the tile holds is
+//   u_k = sum_x w0_k[x] H[x][k],   H[(comp, x)][k] = sum_j G_comp[x][j] B[j][k],
+// with B[j][k] = w1_k[y] (2D, j = y) or w1_k[y] w2_k[z] (3D, j = 4y + z): H is a 16 x 16 x 16
+// product for each group of 16 nodes (four v_mfma_f64_16x16x4 steps), the tile values G sit in
+// registers as the A operand, B comes from LDS.  The contraction with w0 is a 4-term dot product
+// per lane plus one lane exchange; the node's complex sum is added to its FP64 accumulator, which
+// the per-node epilogue then turns into c_k (or rhohat_k).
+template <typename T, int MSP, int DIM>
+__global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict__ grid, long long gstride,
+                                                        double2* __restrict__ acc, long long astride,
+                                                        NodeArgs na, const GItem* __restrict__ items, int nitems,
+                                                        const int* __restrict__ cand, double qq) {
+    __shared__ double W1T[16][kMChunk];   // B operand, one row per tile column j
+    __shared__ double W0T[8][kMChunk];    // w0 per tile row x
+    __shared__ int nodes[kMChunk];
     const int iid = chunk_id(nitems);
     if (iid >= nitems) return;
     const GItem it = items[iid];
     const int b = blockIdx.y;
     const int t = threadIdx.x;
-    const int o0 = it.g0 * GT, o1 = it.g1 * GT, o2 = it.g2 * GT;
-    if (t < it.count) {
-        const int node = cand[it.start + t];
-        double w0[GT], w1[GT], w2[GT];
-        tile_weights<MSP, GT>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
-        tile_weights<MSP, GT>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
-        tile_weights<MSP, GT>(na.s[2][node], o2, na.Mr[2], na.gc.alpha, qq, w2);
-        const V2<T> c = cbuf[(long long)b * cstride + node];
-#pragma unroll
-        for (int k = 0; k < GT; ++k) {
-            A[t][k] = make_double2((double)c.x * w0[k], (double)c.y * w0[k]);
-            Bw[t][k] = w1[k];
-            Cw[t][k] = w2[k];
-        }
-    }
-    __syncthreads();
+    const int o0 = it.g0 * 8;
+    const int o1 = it.g1 * (DIM == 2 ? 16 : 4);
+    const int o2 = it.g2 * 4;
+    const int k = t & (kMChunk - 1);
+    // A operand: lane l holds G_comp[x][j] for comp = (l mod 16) / 8, x = l mod 8, j = 4 s + l / 16
     const int wv = t >> 6, lane = t & 63;
-    const int i0 = lane >> 4, i1 = (lane >> 2) & 3, i2 = lane & 3;
-    const int m0 = wv * 64, m1 = min(it.count, m0 + 64);
-    double ax = 0, ay = 0;
-    for (int m = m0; m < m1; ++m) {
-        const double2 a = A[m][i0];
-        const double bw = Bw[m][i1] * Cw[m][i2];
-        ax += a.x * bw;
-        ay += a.y * bw;
-    }
-    part[wv][lane] = make_double2(ax, ay);
-    __syncthreads();
-    if (t < 64) {
-        double sx = 0, sy = 0;
+    const int ia = lane & 15, ka = lane >> 4;
+    const T* g = reinterpret_cast<const T*>(grid + (long long)b * gstride);
+    double av[4];
 #pragma unroll
-        for (int q = 0; q < kGChunk / 64; ++q) {
-            sx += part[q][t].x;
-            sy += part[q][t].y;
+    for (int st = 0; st < 4; ++st) {
+        const int j = 4 * st + ka;
+        const int x = o0 + (ia & 7);
+        long long cell;
+        if (DIM == 2)
+            cell = (long long)x * na.Mr[1] + o1 + j;
+        else
+            cell = ((long long)x * na.Mr[1] + o1 + (j >> 2)) * na.Mr[2] + o2 + (j & 3);
+        av[st] = (double)g[2 * cell + (ia >> 3)];
+    }
+    for (int base = 0; base < it.count; base += kMChunk) {
+        const int cnt = min(kMChunk, it.count - base);
+        if (base > 0) __syncthreads();   // the previous block has read W0T, W1T and nodes
+        if (t < kMChunk) {
+            double w0[8];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) w0[x] = 0.0;
+            int node = 0;
+            if (k < cnt) {
+                node = cand[it.start + base + k];
+                tile_weights<MSP, 8>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
+            }
+            nodes[k] = node;
+#pragma unroll
+            for (int x = 0; x < 8; ++x) W0T[x][k] = w0[x];
+        } else {
+            double w1[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) w1[j] = 0.0;
+            if (k < cnt) {
+                const int node = cand[it.start + base + k];
+                if (DIM == 2) {
+                    tile_weights<MSP, 16>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
+                } else {
+                    double a1[4], a2[4];
+                    tile_weights<MSP, 4>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, a1);
+                    tile_weights<MSP, 4>(na.s[2][node], o2, na.Mr[2], na.gc.alpha, qq, a2);
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+#pragma unroll
+                        for (int z = 0; z < 4; ++z) w1[4 * y + z] = a1[y] * a2[z];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) W1T[j][k] = w1[j];
         }
-        if (sx != 0.0 || sy != 0.0) {
-            const int c0 = o0 + (t >> 4), c1 = o1 + ((t >> 2) & 3), c2 = o2 + (t & 3);
-            TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride +
-                                            ((long long)c0 * na.Mr[1] + c1) * na.Mr[2] + c2);
-            global_add<TG>(dst, (TG)sx);
-            global_add<TG>(dst + 1, (TG)sy);
+        __syncthreads();
+#pragma unroll
+        for (int gi = 0; gi < kMChunk / 64; ++gi) {
+            const int k0 = 16 * (wv + 4 * gi);
+            if (k0 >= cnt) break;
+            d4_t hacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+                hacc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], W1T[4 * st + ka][k0 + ia], hacc, 0, 0, 0);
+            // register v of lane l holds H[i][k0 + l mod 16] with i = 4 v + l / 16, i.e.
+            // (comp, x) = (0, ka), (0, 4 + ka), (1, ka), (1, 4 + ka) for v = 0..3
+            const double wa = W0T[ka][k0 + ia], wb = W0T[4 + ka][k0 + ia];
+            double pre = wa * hacc[0] + wb * hacc[1];
+            double pim = wa * hacc[2] + wb * hacc[3];
+            pre += __shfl_xor(pre, 16);
+            pim += __shfl_xor(pim, 16);
+            pre += __shfl_xor(pre, 32);
+            pim += __shfl_xor(pim, 32);
+            if (ka < 2 && k0 + ia < cnt) {
+                double* dst = reinterpret_cast<double*>(acc + (long long)b * astride + nodes[k0 + ia]) + ka;
+                global_add<double>(dst, ka == 0 ? pre : pim);
+            }
         }
+    }
+}
+
+// per-node epilogue of the tile-gathered interpolation
+template <typename T>
+__global__ void k_iepilogue(const double2* __restrict__ acc, long long astride, long long Mh, NodeArgs na,
+                            EpiArgs ea) {
+    const int b = blockIdx.y;
+    for (long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x; node < Mh;
+         node += (long long)gridDim.x * blockDim.x) {
+        const double2 v = acc[(long long)b * astride + node];
+        epilogue<T>(ea, b, (int)node, v.x, v.y, na.s[0][node], na.s[1][node]);
     }
 }
 
@@ -627,6 +742,24 @@ static int grid_chunks(const nlf_plan* p) { return ((p->nchunks + 7) / 8) * 8; }
 template <typename T, int MSP>
 static int interp_t(nlf_plan* p, const EpiArgs& ea) {
     NodeArgs na = node_args(p);
+    if (p->use_gather) {
+        NLF_TRY(fill_zero(p, p->iacc, (size_t)p->batch * p->Mh * 2 * sizeof(double)));
+        dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
+        const double qq = exp(-2.0 * p->gc.alpha);
+        const V2<T>* g = reinterpret_cast<const V2<T>*>(p->grid_a);
+        if (p->dim == 2)
+            hipLaunchKernelGGL((k_minterp<T, MSP, 2>), ggrid, dim3(2 * kMChunk), 0, p->stream, g, p->G,
+                               (double2*)p->iacc, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+        else
+            hipLaunchKernelGGL((k_minterp<T, MSP, 3>), ggrid, dim3(2 * kMChunk), 0, p->stream, g, p->G,
+                               (double2*)p->iacc, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+        NLF_HIP(hipGetLastError());
+        dim3 egrid((unsigned)std::min<long long>((p->Mh + 255) / 256, 4096), p->batch);
+        hipLaunchKernelGGL((k_iepilogue<T>), egrid, dim3(256), 0, p->stream, (const double2*)p->iacc, p->Mh, p->Mh,
+                           na, ea);
+        NLF_HIP(hipGetLastError());
+        return NLF_OK;
+    }
     dim3 grid(grid_chunks(p), p->batch);
     const V2<T>* g = reinterpret_cast<const V2<T>*>(p->grid_a);
     if (p->dim == 2)
@@ -647,14 +780,14 @@ static int spread_t(nlf_plan* p) {
         const double qq = exp(-2.0 * p->gc.alpha);
         if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid (3D)
             double2* g64 = reinterpret_cast<double2*>(p->grid_b);
-            hipLaunchKernelGGL((k_gspread3<T, double, MSP>), ggrid, dim3(kGChunk), 0, p->stream, g64, p->G, c, p->Mh,
-                               na, p->gitems, p->ngitems, p->gcand, qq);
+            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3>), ggrid, dim3(2 * kMChunk), 0, p->stream, g64, p->G, c,
+                               p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
         } else if (p->dim == 2) {
-            hipLaunchKernelGGL((k_gspread2<T, T, MSP>), ggrid, dim3(kGChunk), 0, p->stream, g, p->G, c, p->Mh, na,
-                               p->gitems, p->ngitems, p->gcand, qq);
+            hipLaunchKernelGGL((k_mspread<T, T, MSP, 2>), ggrid, dim3(2 * kMChunk), 0, p->stream, g, p->G, c, p->Mh,
+                               na, p->gitems, p->ngitems, p->gcand, qq);
         } else {
-            hipLaunchKernelGGL((k_gspread3<T, T, MSP>), ggrid, dim3(kGChunk), 0, p->stream, g, p->G, c, p->Mh, na,
-                               p->gitems, p->ngitems, p->gcand, qq);
+            hipLaunchKernelGGL((k_mspread<T, T, MSP, 3>), ggrid, dim3(2 * kMChunk), 0, p->stream, g, p->G, c, p->Mh,
+                               na, p->gitems, p->ngitems, p->gcand, qq);
         }
         NLF_HIP(hipGetLastError());
         return NLF_OK;

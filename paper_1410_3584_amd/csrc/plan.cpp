@@ -292,7 +292,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         const long long kMaxCand = 400000000LL;
         int gt[3], ng[3];
         for (int i = 0; i < 3; ++i) {
-            gt[i] = (i < p->dim) ? std::min((p->dim == 2 ? 8 : 4), p->Mr[i]) : 1;
+            gt[i] = (i >= p->dim) ? 1 : (i == 0 ? 8 : (p->dim == 2 ? 16 : 4));   // Mr >= 16 always
             p->gtile[i] = gt[i];
             ng[i] = (i < p->dim) ? p->Mr[i] / gt[i] : 1;
         }
@@ -353,12 +353,12 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
                 int g2 = (int)(t % ng[2]);
                 int g1 = (int)((t / ng[2]) % ng[1]);
                 int g0 = (int)(t / ((long long)ng[2] * ng[1]));
-                for (long long s0 = beg; s0 < end; s0 += kGChunk) {
+                for (long long s0 = beg; s0 < end; s0 += kMItem) {
                     GItem it;
                     it.g0 = g0;
                     it.g1 = g1;
                     it.g2 = g2;
-                    it.count = (int)std::min<long long>(kGChunk, end - s0);
+                    it.count = (int)std::min<long long>(kMItem, end - s0);
                     it.start = s0;
                     items.push_back(it);
                 }
@@ -409,6 +409,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_TRY(dev_alloc(p, &p->cbuf, (size_t)p->batch * Mh * es));
+    if (p->use_gather) NLF_TRY(dev_alloc(p, (void**)&p->iacc, (size_t)p->batch * Mh * 2 * sizeof(double)));
     for (int i = 0; i < p->dim; ++i) NLF_TRY(upload(p, (void**)&p->s[i], ss[i].data(), Mh * sizeof(double)));
     NLF_TRY(upload(p, (void**)&p->wfac, wf.data(), Mh * sizeof(double)));
     if (kernel == NLF_LAPLACE2D) NLF_TRY(upload(p, (void**)&p->gk, gk.data(), Mh * sizeof(double)));
