@@ -51,7 +51,7 @@ struct GItem {
     long long start;   // first entry in the candidate list
 };
 constexpr int kMChunk = 128;
-constexpr int kMItem = 8 * kMChunk;
+constexpr int kMItem = 1024;
 
 // Gaussian-gridding constants handed to the kernels by value.
 struct GaussConst {

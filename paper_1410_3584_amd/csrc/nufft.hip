@@ -12,8 +12,10 @@
 // computed with v_mfma_f64_16x16x4 from weights staged in LDS; tiles receive their sums with
 // one atomic per cell component, nodes with one per component and tile.  The symbol/weight
 // multiply (the symbol_weight step) is the per-node epilogue of the interpolation, in FP64.
-// Fallback (candidate list too large): node-parallel kernels over binned chunks, the grid window
-// staged in LDS (interpolation) or LDS atomics (spreading).
+// 2D interpolation works per bin of nodes instead (k_binterp2): the bin's grid window in LDS is
+// the A operand and the nodes' weights the B operand, with no atomics.
+// Fallback (candidate list too large, 3D): node-parallel kernels over binned chunks, the grid
+// window staged in LDS (interpolation) or LDS atomics (spreading).
 // Only half of the node set is evaluated: rho is real, so rhohat(-k) = conj(rhohat(k)), and the
 // node set is symmetric under k -> -k (even n_phi, symmetric Gauss-Legendre in cos theta).
 #include <algorithm>
@@ -28,6 +30,9 @@ template <> __device__ __forceinline__ float2 mk2<float>(float x, float y) { ret
 template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) { return make_double2(x, y); }
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// candidates per block of the tile-gathered spreading (two threads per candidate)
+constexpr int kSpreadBlock = 64;
 
 // index modulo an oversampled grid extent (always a power of two)
 __device__ __forceinline__ int wrap(int v, int M) { return v & (M - 1); }
@@ -136,51 +141,6 @@ __device__ __forceinline__ void epilogue(const EpiArgs& e, int batch, int node, 
 }
 
 // ---- interpolation ----------------------------------------------------------------------------
-template <typename T, int MSP>
-__global__ void __launch_bounds__(kChunk) k_interp2(const V2<T>* __restrict__ grid, long long gstride,
-                                                    NodeArgs na, EpiArgs ea) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    V2<T>* win = reinterpret_cast<V2<T>*>(smem_raw);
-    const int cid = chunk_id(na.nchunks);
-    if (cid >= na.nchunks) return;
-    const Chunk ch = na.chunks[cid];
-    const int b = blockIdx.y;
-    const V2<T>* g = grid + (long long)b * gstride;
-    const int W0 = na.W[0], W1 = na.W[1];
-    const int o0 = ch.t0 * na.tile[0] - MSP + 1, o1 = ch.t1 * na.tile[1] - MSP + 1;
-    for (int idx = threadIdx.x; idx < W0 * W1; idx += kChunk) {
-        int r = idx / W1, c = idx - r * W1;
-        win[idx] = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
-    }
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t >= ch.count) return;
-    const int node = ch.start + t;
-    const double sv0 = na.s[0][node], sv1 = na.s[1][node];
-    T w0[2 * MSP], w1[2 * MSP];
-    int l0, l1;
-    gauss_weights<T, MSP>(sv0, na.gc, w0, l0);
-    gauss_weights<T, MSP>(sv1, na.gc, w1, l1);
-    const int r0 = wrap(l0, na.Mr[0]) - ch.t0 * na.tile[0];
-    const int r1 = wrap(l1, na.Mr[1]) - ch.t1 * na.tile[1];
-    T ax = 0, ay = 0;
-    const V2<T>* base = win + r0 * W1 + r1;
-#pragma unroll
-    for (int i = 0; i < 2 * MSP; ++i) {
-        T rx = 0, ry = 0;
-        const V2<T>* row = base + i * W1;
-#pragma unroll
-        for (int j = 0; j < 2 * MSP; ++j) {
-            V2<T> v = row[j];
-            rx += v.x * w1[j];
-            ry += v.y * w1[j];
-        }
-        ax += w0[i] * rx;
-        ay += w0[i] * ry;
-    }
-    epilogue<T>(ea, b, node, (double)ax, (double)ay, sv0, sv1);
-}
-
 template <typename T, int MSP>
 __global__ void __launch_bounds__(kChunk) k_interp3(const V2<T>* __restrict__ grid, long long gstride,
                                                     NodeArgs na, EpiArgs ea) {
@@ -382,30 +342,31 @@ __global__ void __launch_bounds__(kChunk) k_spread3(V2<T>* __restrict__ grid, lo
 }
 
 // ---- output-driven spreading (gather over candidate nodes, no LDS atomics) ----------------------
-// Weights of one node along one axis restricted to the GT cells o..o+GT-1 of a gather tile:
-// w[k] = sum over p == o + k - l0 (mod Mr), p in [-msp+1, msp], of exp(-alpha (p - delta)^2).
-// When Mr >= 2 msp + GT the representative is unique and consecutive, so the Gaussian is stepped
-// by its ratio exp(-alpha (2 (p - delta) + 1)), itself stepped by exp(-2 alpha) (two exps per axis).
+// Weights of one node along one axis on the GT cells o..o+GT-1 of a gather tile.
+// When Mr >= 2 msp + GT every cell has one offset p = (cell - l0) mod Mr near the stencil, and the
+// weight is exp(-alpha (p - delta)^2), stepped by its ratio exp(-alpha (2 (p - delta) + 1)), itself
+// stepped by exp(-2 alpha) (two exps per axis, two multiplies per cell).  Cells of the tile outside
+// the node's 2 msp stencil keep their Gaussian weight instead of 0: it is below e^{-3 pi msp / 4},
+// the truncation level of the stencil itself.  Otherwise (small grids, where the stencil wraps onto
+// itself) the weight is the sum over the stencil offsets p == cell - l0 (mod Mr), p in [-msp+1, msp].
 template <int MSP, int GT>
 __device__ __forceinline__ void tile_weights(double s, int o, int Mr, double alpha, double qq, double (&w)[GT]) {
     const double f = floor(s);
     const int l0 = (int)f;
     const double d = s - f;
     if (Mr >= 2 * MSP + GT) {
+        // offset of cell o: the representative in (msp - Mr, msp], which holds every offset a tile
+        // overlapping the stencil can have (-msp - GT + 2 .. msp)
         int p0 = wrap(o - l0 + MSP - 1, Mr) - MSP + 1;
-        int q0 = (p0 > MSP) ? p0 - Mr : p0;
-        int ks = max(0, -MSP + 1 - q0);
-        double x = (double)(q0 + ks) - d;
+        if (p0 > MSP) p0 -= Mr;
+        double x = (double)p0 - d;
         double g = exp(-alpha * x * x);
         double r = exp(-alpha * (2.0 * x + 1.0));
 #pragma unroll
         for (int k = 0; k < GT; ++k) {
-            const int pk = q0 + k;
-            w[k] = (k >= ks && pk <= MSP) ? g : 0.0;
-            if (k >= ks) {
-                g *= r;
-                r *= qq;
-            }
+            w[k] = g;
+            g *= r;
+            r *= qq;
         }
     } else {
 #pragma unroll
@@ -436,13 +397,15 @@ __device__ __forceinline__ int mrow_slot(int k, int chunk) {
     return ((chunk ^ ((k >> 1) & 7) ^ ((k & 1) << 2)) & 7);
 }
 
-template <typename T, typename TG, int MSP, int DIM>
-__global__ void __launch_bounds__(2 * kMChunk) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
+template <typename T, typename TG, int MSP, int DIM, int KC>
+__global__ void __launch_bounds__(2 * KC) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
                                                         const int* __restrict__ cand, double qq) {
-    static_assert(kMChunk % 16 == 0, "four waves, whole MFMA steps each");
-    __shared__ __align__(16) double S[2 * kMChunk * 16];
+    constexpr int NW = 2 * KC / 64;   // waves; each multiplies KC / NW candidates of a block
+    static_assert(KC % (4 * NW) == 0 && (KC / NW) % 8 == 0, "whole pairs of MFMA steps per wave");
+    static_assert(2 * KC * 16 >= NW * 4 * 64, "wave partials fit S");
+    __shared__ __align__(16) double S[2 * KC * 16];
     const int iid = chunk_id(nitems);
     if (iid >= nitems) return;
     const GItem it = items[iid];
@@ -451,56 +414,72 @@ __global__ void __launch_bounds__(2 * kMChunk) k_mspread(V2<TG>* __restrict__ gr
     const int o0 = it.g0 * 8;
     const int o1 = it.g1 * (DIM == 2 ? 16 : 4);
     const int o2 = it.g2 * 4;
-    const int k = t & (kMChunk - 1);
-    const bool is_a = t < kMChunk;
+    const int k = t & (KC - 1);
+    const bool is_a = t < KC;
     const int wv = t >> 6, lane = t & 63;
     const int r = lane & 15;
-    const int kb = wv * (kMChunk / 4);
+    const int kb = wv * (KC / NW);
     d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    for (int base = 0; base < it.count; base += kMChunk) {
-        const int cnt = min(kMChunk, it.count - base);
+    // node data of this thread's candidate in the current block, loaded one block ahead so that
+    // the loads overlap the previous block's matrix products
+    double sa = 0.0, sb = 0.0;
+    V2<T> cv = mk2<T>((T)0, (T)0);
+    auto fetch = [&](int base) {
+        if (base + k < it.count) {
+            const int node = cand[it.start + base + k];
+            if (is_a) {
+                sa = na.s[0][node];
+                cv = cbuf[(long long)b * cstride + node];
+            } else {
+                sa = na.s[1][node];
+                if (DIM == 3) sb = na.s[2][node];
+            }
+        }
+    };
+    fetch(0);
+    for (int base = 0; base < it.count; base += KC) {
+        const int cnt = min(KC, it.count - base);
         if (base > 0) __syncthreads();   // the previous block's products have read S
         double row[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) row[j] = 0.0;
         if (k < cnt) {
-            const int node = cand[it.start + base + k];
             if (is_a) {
                 double w0[8];
-                tile_weights<MSP, 8>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
-                const V2<T> c = cbuf[(long long)b * cstride + node];
-                const double cx = (double)c.x, cy = (double)c.y;
+                tile_weights<MSP, 8>(sa, o0, na.Mr[0], na.gc.alpha, qq, w0);
+                const double cx = (double)cv.x, cy = (double)cv.y;
 #pragma unroll
                 for (int x = 0; x < 8; ++x) {
                     row[x] = cx * w0[x];
                     row[8 + x] = cy * w0[x];
                 }
             } else if (DIM == 2) {
-                tile_weights<MSP, 16>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, row);
+                tile_weights<MSP, 16>(sa, o1, na.Mr[1], na.gc.alpha, qq, row);
             } else {
                 double w1[4], w2[4];
-                tile_weights<MSP, 4>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
-                tile_weights<MSP, 4>(na.s[2][node], o2, na.Mr[2], na.gc.alpha, qq, w2);
+                tile_weights<MSP, 4>(sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
+                tile_weights<MSP, 4>(sb, o2, na.Mr[2], na.gc.alpha, qq, w2);
 #pragma unroll
                 for (int y = 0; y < 4; ++y)
 #pragma unroll
                     for (int z = 0; z < 4; ++z) row[4 * y + z] = w1[y] * w2[z];
             }
         }
-        double* mine = S + (is_a ? 0 : kMChunk * 16) + k * 16;
+        double* mine = S + (is_a ? 0 : KC * 16) + k * 16;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             *reinterpret_cast<double2*>(mine + 2 * mrow_slot(k, c)) = make_double2(row[2 * c], row[2 * c + 1]);
         __syncthreads();
+        fetch(base + KC);
         if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
-            constexpr int kSteps = kMChunk / 16;
+            constexpr int kSteps = KC / NW / 4;
             double av[kSteps], bv[kSteps];
 #pragma unroll
             for (int q = 0; q < kSteps; ++q) {
                 const int kk = kb + 4 * q + (lane >> 4);
                 const int off = kk * 16 + 2 * mrow_slot(kk, r >> 1) + (r & 1);
                 av[q] = S[off];
-                bv[q] = S[kMChunk * 16 + off];
+                bv[q] = S[KC * 16 + off];
             }
 #pragma unroll
             for (int q = 0; q < kSteps; q += 2) {
@@ -514,12 +493,13 @@ __global__ void __launch_bounds__(2 * kMChunk) k_mspread(V2<TG>* __restrict__ gr
 #pragma unroll
     for (int v = 0; v < 4; ++v) S[(wv * 4 + v) * 64 + lane] = acc[v];
     __syncthreads();
-    {
-        // v_mfma_f64_16x16x4 leaves element (i, j) of the 16 x 16 product in register v = i / 4 of
-        // lane l = 16 (i mod 4) + j
-        const int v = t >> 6, l = t & 63;
-        const double sum = S[(0 * 4 + v) * 64 + l] + S[(1 * 4 + v) * 64 + l] + S[(2 * 4 + v) * 64 + l] +
-                           S[(3 * 4 + v) * 64 + l];
+    // v_mfma_f64_16x16x4 leaves element (i, j) of the 16 x 16 product in register v = i / 4 of
+    // lane l = 16 (i mod 4) + j
+    for (int o = t; o < 256; o += 2 * KC) {
+        const int v = o >> 6, l = o & 63;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += S[(w * 4 + v) * 64 + l];
         const int i = 4 * v + (l >> 4), j = l & 15;
         if (sum != 0.0) {
             const int x = o0 + (i & 7);
@@ -530,6 +510,122 @@ __global__ void __launch_bounds__(2 * kMChunk) k_mspread(V2<TG>* __restrict__ gr
                 cell = ((long long)x * na.Mr[1] + o1 + (j >> 2)) * na.Mr[2] + o2 + (j & 3);
             TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride + cell) + (i >> 3);
             global_add<TG>(dst, (TG)sum);
+        }
+    }
+}
+
+// ---- 2D interpolation on the FP64 matrix cores, one workgroup per bin of nodes -----------------
+// The nodes of one chunk have l0 in the same 8 x 16 bin, so their stencils lie in one window of
+// (8 + 2 msp - 1) x (16 + 2 msp - 1) cells, staged in LDS as FP64 real and imaginary planes.  For
+// a group of 16 nodes and an 8-row block of the window,
+//   H[(comp, x)][k] = sum_y G_comp[x][y] w1_k[y]
+// is a 16 x 16 x (4 KS) product (KS v_mfma_f64_16x16x4 steps; A = window values, B = the nodes'
+// y-weights, zero outside each stencil), and u_k = sum_x w0_k[x] H[x][k] accumulates in registers
+// over the row blocks.  Wave w owns groups w, w + 4: lane (ia, ka) = (l mod 16, l / 16) holds node
+// 16 g + ia, its y-weights on columns 4 st + ka and its x-weights on rows 4 m + ka, both from the
+// Gaussian recurrence g(x + 4) = g(x) exp(-alpha (8 x + 16)), whose ratio steps by exp(-32 alpha)
+// (four exps per lane and group).  The node's complex sum goes through the FP64 epilogue (symbol
+// times weight) directly: no atomics, no cross-wave reduction.
+template <typename T, int MSP>
+__global__ void __launch_bounds__(256) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
+                                                 NodeArgs na, EpiArgs ea, double qq4) {
+    constexpr int WX = 8 + 2 * MSP - 1, RBX = (WX + 7) / 8;
+    constexpr int WY = 16 + 2 * MSP - 1, KS = (WY + 3) / 4;
+    // window planes (real, imaginary), column-major: Gp[p * PL + c * PX + r]; PX = 8 mod 32 and
+    // PL = 16 mod 32 doubles make each A-operand load (8 rows x 4 columns x 2 planes) conflict-free
+    constexpr int NRW = 8 * RBX, NCW = 4 * KS;
+    constexpr int PX = NRW + ((8 - NRW % 32) + 32) % 32;
+    constexpr int PL = NCW * PX + 16;
+    __shared__ double Gp[2 * PL];
+    __shared__ double nd[kChunk][2];        // fractional parts delta_0, delta_1
+    __shared__ int noff[kChunk][2];         // stencil start within the window
+    const int cid = chunk_id(na.nchunks);
+    if (cid >= na.nchunks) return;
+    const Chunk ch = na.chunks[cid];
+    const int b = blockIdx.y;
+    const int t = threadIdx.x;
+    const V2<T>* g = grid + (long long)b * gstride;
+    const int o0 = ch.t0 * 8 - (MSP - 1), o1 = ch.t1 * 16 - (MSP - 1);
+    for (int idx = t; idx < NRW * NCW; idx += 256) {
+        const int r = idx / NCW, c = idx - r * NCW;
+        const V2<T> v = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
+        Gp[c * PX + r] = (double)v.x;
+        Gp[PL + c * PX + r] = (double)v.y;
+    }
+    if (t < ch.count) {
+        const int node = ch.start + t;
+        const double s0 = na.s[0][node], s1 = na.s[1][node];
+        const double f0 = floor(s0), f1 = floor(s1);
+        nd[t][0] = s0 - f0;
+        nd[t][1] = s1 - f1;
+        noff[t][0] = wrap((int)f0, na.Mr[0]) - ch.t0 * 8;    // in [0, 8)
+        noff[t][1] = wrap((int)f1, na.Mr[1]) - ch.t1 * 16;   // in [0, 16)
+    }
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63;
+    const int ia = lane & 15, ka = lane >> 4;
+    const double alpha = na.gc.alpha;
+    const double* arow = &Gp[(ia >> 3) * PL + ka * PX + (ia & 7)];   // A operand of row block 0, step 0
+    for (int k0 = 16 * wv; k0 < ch.count; k0 += 64) {
+        const int jn = k0 + ia;
+        double bv[KS], wx[2 * RBX];
+        if (jn < ch.count) {
+            const double d0 = nd[jn][0], d1 = nd[jn][1];
+            const int rx0 = noff[jn][0], ry0 = noff[jn][1];
+            {   // y-weights of columns 4 st + ka: stencil offset q = 4 st + ka - ry0 in [0, 2 msp)
+                const int q0 = ka - ry0;
+                const double x0 = (double)(q0 - (MSP - 1)) - d1;
+                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
+#pragma unroll
+                for (int st = 0; st < KS; ++st) {
+                    const int q = q0 + 4 * st;
+                    bv[st] = (q >= 0 && q < 2 * MSP) ? gg : 0.0;
+                    gg *= rr;
+                    rr *= qq4;
+                }
+            }
+            {   // x-weights of rows 4 m + ka
+                const int q0 = ka - rx0;
+                const double x0 = (double)(q0 - (MSP - 1)) - d0;
+                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
+#pragma unroll
+                for (int m = 0; m < 2 * RBX; ++m) {
+                    const int q = q0 + 4 * m;
+                    wx[m] = (q >= 0 && q < 2 * MSP) ? gg : 0.0;
+                    gg *= rr;
+                    rr *= qq4;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int st = 0; st < KS; ++st) bv[st] = 0.0;
+#pragma unroll
+            for (int m = 0; m < 2 * RBX; ++m) wx[m] = 0.0;
+        }
+        double pre = 0.0, pim = 0.0;
+#pragma unroll
+        for (int rb = 0; rb < RBX; ++rb) {
+            d4_t h0 = {0.0, 0.0, 0.0, 0.0}, h1 = h0;
+#pragma unroll
+            for (int st = 0; st + 1 < KS; st += 2) {
+                h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[8 * rb + 4 * st * PX], bv[st], h0, 0, 0, 0);
+                h1 = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[8 * rb + (4 * st + 4) * PX], bv[st + 1], h1, 0, 0, 0);
+            }
+            if (KS & 1)
+                h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[8 * rb + 4 * (KS - 1) * PX], bv[KS - 1], h0, 0, 0, 0);
+            const d4_t h = h0 + h1;
+            // register v of lane l holds H[i][l mod 16], i = 4 v + l / 16, within the row block:
+            // (comp, x) = (0, ka), (0, 4 + ka), (1, ka), (1, 4 + ka); rows 8 rb + ka = 4 (2 rb) + ka
+            pre += wx[2 * rb] * h[0] + wx[2 * rb + 1] * h[1];
+            pim += wx[2 * rb] * h[2] + wx[2 * rb + 1] * h[3];
+        }
+        pre += __shfl_xor(pre, 16);
+        pim += __shfl_xor(pim, 16);
+        pre += __shfl_xor(pre, 32);
+        pim += __shfl_xor(pim, 32);
+        if (ka == 0 && jn < ch.count) {
+            const int node = ch.start + jn;
+            epilogue<T>(ea, b, node, pre, pim, na.s[0][node], na.s[1][node]);
         }
     }
 }
@@ -742,6 +838,14 @@ static int grid_chunks(const nlf_plan* p) { return ((p->nchunks + 7) / 8) * 8; }
 template <typename T, int MSP>
 static int interp_t(nlf_plan* p, const EpiArgs& ea) {
     NodeArgs na = node_args(p);
+    if (p->dim == 2) {
+        dim3 grid(grid_chunks(p), p->batch);
+        const double qq4 = exp(-32.0 * p->gc.alpha);
+        hipLaunchKernelGGL((k_binterp2<T, MSP>), grid, dim3(256), 0, p->stream,
+                           reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4);
+        NLF_HIP(hipGetLastError());
+        return NLF_OK;
+    }
     if (p->use_gather) {
         NLF_TRY(fill_zero(p, p->iacc, (size_t)p->batch * p->Mh * 2 * sizeof(double)));
         dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
@@ -762,10 +866,7 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea) {
     }
     dim3 grid(grid_chunks(p), p->batch);
     const V2<T>* g = reinterpret_cast<const V2<T>*>(p->grid_a);
-    if (p->dim == 2)
-        hipLaunchKernelGGL((k_interp2<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, na, ea);
-    else
-        hipLaunchKernelGGL((k_interp3<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, na, ea);
+    hipLaunchKernelGGL((k_interp3<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, na, ea);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -780,13 +881,13 @@ static int spread_t(nlf_plan* p) {
         const double qq = exp(-2.0 * p->gc.alpha);
         if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid (3D)
             double2* g64 = reinterpret_cast<double2*>(p->grid_b);
-            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3>), ggrid, dim3(2 * kMChunk), 0, p->stream, g64, p->G, c,
+            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, kSpreadBlock>), ggrid, dim3(2 * kSpreadBlock), 0, p->stream, g64, p->G, c,
                                p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
         } else if (p->dim == 2) {
-            hipLaunchKernelGGL((k_mspread<T, T, MSP, 2>), ggrid, dim3(2 * kMChunk), 0, p->stream, g, p->G, c, p->Mh,
+            hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, kSpreadBlock>), ggrid, dim3(2 * kSpreadBlock), 0, p->stream, g, p->G, c, p->Mh,
                                na, p->gitems, p->ngitems, p->gcand, qq);
         } else {
-            hipLaunchKernelGGL((k_mspread<T, T, MSP, 3>), ggrid, dim3(2 * kMChunk), 0, p->stream, g, p->G, c, p->Mh,
+            hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, kSpreadBlock>), ggrid, dim3(2 * kSpreadBlock), 0, p->stream, g, p->G, c, p->Mh,
                                na, p->gitems, p->ngitems, p->gcand, qq);
         }
         NLF_HIP(hipGetLastError());

@@ -189,8 +189,9 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     }
 
     // tiles
+    // (2D bins of 8 x 16 cells: the matrix-core interpolation stages one bin's window per workgroup)
     for (int i = 0; i < 3; ++i) {
-        int t = (p->dim == 2) ? 16 : 8;
+        int t = (p->dim == 2) ? (i == 0 ? 8 : 16) : 8;
         if (i >= p->dim) t = 1;
         p->tile[i] = std::min(t, p->Mr[i]);
         p->window[i] = (i < p->dim) ? p->tile[i] + 2 * p->msp - 1 : 1;
@@ -409,7 +410,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_TRY(dev_alloc(p, &p->cbuf, (size_t)p->batch * Mh * es));
-    if (p->use_gather) NLF_TRY(dev_alloc(p, (void**)&p->iacc, (size_t)p->batch * Mh * 2 * sizeof(double)));
+    if (p->use_gather && p->dim == 3) NLF_TRY(dev_alloc(p, (void**)&p->iacc, (size_t)p->batch * Mh * 2 * sizeof(double)));
     for (int i = 0; i < p->dim; ++i) NLF_TRY(upload(p, (void**)&p->s[i], ss[i].data(), Mh * sizeof(double)));
     NLF_TRY(upload(p, (void**)&p->wfac, wf.data(), Mh * sizeof(double)));
     if (kernel == NLF_LAPLACE2D) NLF_TRY(upload(p, (void**)&p->gk, gk.data(), Mh * sizeof(double)));
