@@ -398,7 +398,7 @@ __device__ __forceinline__ int mrow_slot(int k, int chunk) {
 }
 
 template <typename T, typename TG, int MSP, int DIM, int KC>
-__global__ void __launch_bounds__(2 * KC) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
+__global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
                                                         const int* __restrict__ cand, double qq) {
@@ -419,7 +419,8 @@ __global__ void __launch_bounds__(2 * KC) k_mspread(V2<TG>* __restrict__ grid, l
     const int wv = t >> 6, lane = t & 63;
     const int r = lane & 15;
     const int kb = wv * (KC / NW);
-    d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    // four accumulators: independent product chains keep the FP64 matrix pipe busy
+    d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
     // node data of this thread's candidate in the current block, loaded one block ahead so that
     // the loads overlap the previous block's matrix products
     double sa = 0.0, sb = 0.0;
@@ -481,14 +482,17 @@ __global__ void __launch_bounds__(2 * KC) k_mspread(V2<TG>* __restrict__ grid, l
                 av[q] = S[off];
                 bv[q] = S[KC * 16 + off];
             }
+            static_assert(kSteps % 4 == 0, "four chains");
 #pragma unroll
-            for (int q = 0; q < kSteps; q += 2) {
+            for (int q = 0; q < kSteps; q += 4) {
                 acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 1], bv[q + 1], acc1, 0, 0, 0);
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 2], bv[q + 2], acc2, 0, 0, 0);
+                acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 3], bv[q + 3], acc3, 0, 0, 0);
             }
         }
     }
-    const d4_t acc = acc0 + acc1;
+    const d4_t acc = (acc0 + acc1) + (acc2 + acc3);
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) S[(wv * 4 + v) * 64 + lane] = acc[v];
@@ -524,16 +528,19 @@ __global__ void __launch_bounds__(2 * KC) k_mspread(V2<TG>* __restrict__ grid, l
 // over the row blocks.  Wave w owns groups w, w + 4: lane (ia, ka) = (l mod 16, l / 16) holds node
 // 16 g + ia, its y-weights on columns 4 st + ka and its x-weights on rows 4 m + ka, both from the
 // Gaussian recurrence g(x + 4) = g(x) exp(-alpha (8 x + 16)), whose ratio steps by exp(-32 alpha)
-// (four exps per lane and group).  The node's complex sum goes through the FP64 epilogue (symbol
-// times weight) directly: no atomics, no cross-wave reduction.
+// (four exps per lane and group).  The plan orders each bin's nodes by column offset, so a group
+// multiplies only the k-steps its nodes' stencils touch.  The node's complex sum goes through the
+// FP64 epilogue (symbol times weight) directly: no atomics, no cross-wave reduction.
 template <typename T, int MSP>
-__global__ void __launch_bounds__(256) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
+__global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
                                                  NodeArgs na, EpiArgs ea, double qq4) {
     constexpr int WX = 8 + 2 * MSP - 1, RBX = (WX + 7) / 8;
     constexpr int WY = 16 + 2 * MSP - 1, KS = (WY + 3) / 4;
     // window planes (real, imaginary), column-major: Gp[p * PL + c * PX + r]; PX = 8 mod 32 and
     // PL = 16 mod 32 doubles make each A-operand load (8 rows x 4 columns x 2 planes) conflict-free
-    constexpr int NRW = 8 * RBX, NCW = 4 * KS;
+    // 4 columns beyond the 4 KS a bin needs: a group's steps start at its first column offset c0
+    // and may run up to 3 columns past its last needed column c1 + 2 msp - 1 <= 15 + 2 msp - 1
+    constexpr int NRW = 8 * RBX, NCW = 4 * KS + 4;
     constexpr int PX = NRW + ((8 - NRW % 32) + 32) % 32;
     constexpr int PL = NCW * PX + 16;
     __shared__ double Gp[2 * PL];
@@ -546,8 +553,10 @@ __global__ void __launch_bounds__(256) k_binterp2(const V2<T>* __restrict__ grid
     const int t = threadIdx.x;
     const V2<T>* g = grid + (long long)b * gstride;
     const int o0 = ch.t0 * 8 - (MSP - 1), o1 = ch.t1 * 16 - (MSP - 1);
+    // lane quads read 4 adjacent columns of one row (64-byte segments); a wave covers 16 rows, so
+    // its column-major LDS stores hit each bank at most twice
     for (int idx = t; idx < NRW * NCW; idx += 256) {
-        const int r = idx / NCW, c = idx - r * NCW;
+        const int c = 4 * (idx / (4 * NRW)) + (idx & 3), r = (idx >> 2) % NRW;
         const V2<T> v = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
         Gp[c * PX + r] = (double)v.x;
         Gp[PL + c * PX + r] = (double)v.y;
@@ -565,15 +574,19 @@ __global__ void __launch_bounds__(256) k_binterp2(const V2<T>* __restrict__ grid
     const int wv = t >> 6, lane = t & 63;
     const int ia = lane & 15, ka = lane >> 4;
     const double alpha = na.gc.alpha;
-    const double* arow = &Gp[(ia >> 3) * PL + ka * PX + (ia & 7)];   // A operand of row block 0, step 0
+    const double* arow = &Gp[(ia >> 3) * PL + ka * PX + (ia & 7)];   // A operand: row block 0, column 0
     for (int k0 = 16 * wv; k0 < ch.count; k0 += 64) {
         const int jn = k0 + ia;
+        // the chunk's nodes are ordered by column offset: the group's columns are
+        // [c0, c1 + 2 msp), with c0, c1 the offsets of its first and last node
+        const int c0 = noff[k0][1], c1 = noff[min(k0 + 15, ch.count - 1)][1];
+        const int ksg = (c1 - c0 + 2 * MSP + 3) >> 2;   // k-steps this group needs (<= KS)
         double bv[KS], wx[2 * RBX];
         if (jn < ch.count) {
             const double d0 = nd[jn][0], d1 = nd[jn][1];
             const int rx0 = noff[jn][0], ry0 = noff[jn][1];
-            {   // y-weights of columns 4 st + ka: stencil offset q = 4 st + ka - ry0 in [0, 2 msp)
-                const int q0 = ka - ry0;
+            {   // y-weights of columns c0 + 4 st + ka: stencil offset q = c0 + 4 st + ka - ry0 in [0, 2 msp)
+                const int q0 = c0 + ka - ry0;
                 const double x0 = (double)(q0 - (MSP - 1)) - d1;
                 double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
 #pragma unroll
@@ -602,22 +615,26 @@ __global__ void __launch_bounds__(256) k_binterp2(const V2<T>* __restrict__ grid
 #pragma unroll
             for (int m = 0; m < 2 * RBX; ++m) wx[m] = 0.0;
         }
+        // one accumulator per row block: independent product chains
+        d4_t h[RBX];
+#pragma unroll
+        for (int rb = 0; rb < RBX; ++rb) h[rb] = d4_t{0.0, 0.0, 0.0, 0.0};
+        const double* acol = arow + c0 * PX;
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            if (st < ksg) {   // uniform over the wave
+#pragma unroll
+                for (int rb = 0; rb < RBX; ++rb)
+                    h[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(acol[8 * rb + 4 * st * PX], bv[st], h[rb], 0, 0, 0);
+            }
+        }
+        // register v of lane l holds H[i][l mod 16], i = 4 v + l / 16, within the row block:
+        // (comp, x) = (0, ka), (0, 4 + ka), (1, ka), (1, 4 + ka); rows 8 rb + ka = 4 (2 rb) + ka
         double pre = 0.0, pim = 0.0;
 #pragma unroll
         for (int rb = 0; rb < RBX; ++rb) {
-            d4_t h0 = {0.0, 0.0, 0.0, 0.0}, h1 = h0;
-#pragma unroll
-            for (int st = 0; st + 1 < KS; st += 2) {
-                h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[8 * rb + 4 * st * PX], bv[st], h0, 0, 0, 0);
-                h1 = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[8 * rb + (4 * st + 4) * PX], bv[st + 1], h1, 0, 0, 0);
-            }
-            if (KS & 1)
-                h0 = __builtin_amdgcn_mfma_f64_16x16x4f64(arow[8 * rb + 4 * (KS - 1) * PX], bv[KS - 1], h0, 0, 0, 0);
-            const d4_t h = h0 + h1;
-            // register v of lane l holds H[i][l mod 16], i = 4 v + l / 16, within the row block:
-            // (comp, x) = (0, ka), (0, 4 + ka), (1, ka), (1, 4 + ka); rows 8 rb + ka = 4 (2 rb) + ka
-            pre += wx[2 * rb] * h[0] + wx[2 * rb + 1] * h[1];
-            pim += wx[2 * rb] * h[2] + wx[2 * rb + 1] * h[3];
+            pre += wx[2 * rb] * h[rb][0] + wx[2 * rb + 1] * h[rb][1];
+            pim += wx[2 * rb] * h[rb][2] + wx[2 * rb + 1] * h[rb][3];
         }
         pre += __shfl_xor(pre, 16);
         pim += __shfl_xor(pim, 16);

@@ -266,6 +266,19 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         std::vector<int> pos(cnt.begin(), cnt.end() - 1);
         for (long long hm = 0; hm < Mh; ++hm) order[pos[bin[hm]]++] = (int)hm;
     }
+    if (p->dim == 2) {
+        // within a 2D bin, order the nodes by their axis-1 cell (then axis-0 cell): 16 consecutive
+        // nodes then span few columns, and the interpolation multiplies only the columns they touch
+        auto cell = [&](int hm, int i) {
+            long long l0 = (long long)std::floor(sh[i][hm]);
+            return (int)(((l0 % p->Mr[i]) + p->Mr[i]) % p->Mr[i]);
+        };
+        for (long long b = 0; b < nbins; ++b)
+            std::stable_sort(order.begin() + cnt[b], order.begin() + cnt[b + 1], [&](int a, int c) {
+                const int ya = cell(a, 1), yc = cell(c, 1);
+                return ya != yc ? ya < yc : cell(a, 0) < cell(c, 0);
+            });
+    }
     std::vector<Chunk> chunks;
     for (long long b = 0; b < nbins; ++b) {
         int beg = cnt[b], end = cnt[b + 1];
