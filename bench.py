@@ -61,7 +61,7 @@ def blas_threads():
     return os.cpu_count()
 
 
-def cpu_baseline(n, L, rho, frac=4):
+def cpu_baseline(n, L, rho, frac=2):
     """Time the FP64 oracle (direct sums) on 1/frac of the node set of the K2 evaluation and
     extrapolate linearly in the node count (both direct sums are linear in M)."""
     from oracle import potential as op
