@@ -70,6 +70,7 @@ struct nlf_plan {
     int n_r, n_theta, n_phi;
     long long N, G, M, Mh;      // grid points, oversampled grid points, nodes, half nodes
     hipStream_t stream;
+    hipStream_t own_stream = nullptr;   // the solvers' graph-capturable stream (see solvers.hip)
     int tile[3];                // bin tile sizes per axis
     int window[3];              // tile + 2 msp - 1
     nlf::GaussConst gc;

@@ -314,7 +314,9 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         auto axis_tiles = [&](double s, int i, int* out) -> int {
             long long l0 = (long long)std::floor(s);
             int cnt = 0;
-            if (2 * p->msp >= p->Mr[i]) {
+            // a stencil longer than Mr - gt + 1 can start and end in one tile while wrapping
+            // through the others: list every tile of the axis
+            if (2 * p->msp + gt[i] > p->Mr[i]) {
                 for (int t = 0; t < ng[i]; ++t) out[cnt++] = t;
                 return cnt;
             }
@@ -571,6 +573,10 @@ int nlf_plan_destroy(nlf_plan* p) {
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->sws && p->sws_free) p->sws_free(p->sws);
     if (p->twin) nlf_plan_destroy(p->twin);
+    if (p->own_stream) {
+        (void)hipStreamSynchronize(p->own_stream);
+        (void)hipStreamDestroy(p->own_stream);
+    }
     for (void* q : p->owned) (void)hipFree(q);
     delete p;
     return NLF_OK;

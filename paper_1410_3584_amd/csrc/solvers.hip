@@ -136,7 +136,7 @@ struct Fld {
     int cg_iters;
     int first;                   // first PCG iteration of the current solve
     int nonfinite;
-    int pad;
+    int steps;                   // outer steps taken while the field was active
 };
 
 __device__ __forceinline__ double trapV(const Geo& g, const Fld& f, const double* Vext, long long i, const double x[3]) {
@@ -206,12 +206,15 @@ __global__ void k_normalize(Geo g, Fld* fl, const T* v, T* phi, T* rho, const do
 // outer residual max|phi^{n+1} - phi^n| / tau; retire the field at eps0.  The next inner solve
 // only needs to be accurate relative to the size of the step it computes, so its tolerance
 // follows the residual down to the caller's tolerance: max(cg_tol, min(1e-3, 1e-3 tau res)).
+// The step count lives on the device (Fld::steps) so that the launch can be replayed from a graph.
 template <typename T>
-__global__ void k_residual_final(Fld* fl, const double* part_r, int nblk, double eps0, int step) {
+__global__ void k_residual_final(Fld* fl, const double* part_r, int nblk, double eps0) {
     const int b = blockIdx.x;
     if (fl[b].done) return;
     double r = max_parts(part_r + b * MAXBLK, nblk);
     if (threadIdx.x == 0) {
+        const int step = fl[b].steps + 1;
+        fl[b].steps = step;
         fl[b].res = r;
         if (!(r == r) || r > 1e300) fl[b].nonfinite = 1;
         if (r <= eps0) {
@@ -642,6 +645,7 @@ struct GsParams {
     double tau, eps0, cg_tol;
     int max_iter, check_every, cg_max;
     int stall_stop;      // retire a field whose residual stopped decreasing (precision floor)
+    int graphs;          // replay captured HIP graphs of the step's launches
 };
 
 static GsParams gs_params(const nlf_plan* p, const nlf_gf_opts* gf) {
@@ -653,12 +657,112 @@ static GsParams gs_params(const nlf_plan* p, const nlf_gf_opts* gf) {
     g.cg_tol = (gf && gf->cg_tol > 0) ? gf->cg_tol : (p->prec == NLF_F64 ? 1e-13 : 1e-6);
     g.cg_max = (gf && gf->cg_max_iter > 0) ? gf->cg_max_iter : 200;
     g.stall_stop = 0;
+    g.graphs = !(gf && gf->no_graph);
     return g;
 }
+
+// A captured sequence of launches on the plan's stream, replayed with one hipGraphLaunch.  Capture
+// records without executing; the body must only enqueue kernels (no synchronisation, no
+// hipMemsetAsync: buffers are cleared by kernels).
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    StepGraph() = default;
+    StepGraph(const StepGraph&) = delete;
+    StepGraph& operator=(const StepGraph&) = delete;
+    ~StepGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// Capture `body` into sg.  Returns false (HIP error state cleared, nothing enqueued) if the
+// stream cannot be captured; the caller then launches directly.
+template <class F>
+static bool capture_graph(nlf_plan* p, StepGraph& sg, F&& body, int* rc) {
+    *rc = NLF_OK;
+    if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    *rc = body();
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->stream, &gr);
+    if (*rc != NLF_OK || e != hipSuccess || !gr) {
+        (void)hipGetLastError();
+        if (gr) (void)hipGraphDestroy(gr);
+        if (*rc == NLF_OK) clear_error();
+        return false;
+    }
+    if (hipGraphInstantiate(&sg.exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(gr);
+        sg.exec = nullptr;
+        return false;
+    }
+    sg.graph = gr;
+    return true;
+}
+
+// Run `body` directly, or (graphs on) capture it on first use and replay the graph.  A capture
+// that fails turns graphs off for the rest of the solve (*graphs = false) and runs `body`.
+template <class F>
+static int run_step(nlf_plan* p, bool* graphs, StepGraph& sg, F&& body) {
+    if (!*graphs) return body();
+    if (!sg.exec) {
+        int rc;
+        if (!capture_graph(p, sg, body, &rc)) {
+            *graphs = false;
+            return body();
+        }
+    }
+    NLF_HIP(hipGraphLaunch(sg.exec, p->stream));
+    return NLF_OK;
+}
+
+// The legacy default stream cannot be captured.  While a solve runs on a plan created on it, the
+// plan's work moves to a stream of its own (non-blocking, default priority), ordered after the
+// caller's stream on entry and before it on exit.
+struct SolveStream {
+    nlf_plan* p;
+    hipStream_t saved = nullptr;
+    bool swapped = false;
+    explicit SolveStream(nlf_plan* pl, bool want) : p(pl) {
+        if (!want || p->stream != nullptr) return;
+        if (!p->own_stream && hipStreamCreateWithFlags(&p->own_stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            p->own_stream = nullptr;
+            return;
+        }
+        if (join(p->own_stream, p->stream)) {
+            saved = p->stream;
+            p->stream = p->own_stream;
+            swapped = true;
+        }
+    }
+    // make `later` wait for the work enqueued so far on `earlier`
+    static bool join(hipStream_t later, hipStream_t earlier) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        bool ok = hipEventRecord(e, earlier) == hipSuccess && hipStreamWaitEvent(later, e, 0) == hipSuccess;
+        (void)hipEventDestroy(e);
+        if (!ok) (void)hipGetLastError();
+        return ok;
+    }
+    ~SolveStream() {
+        if (!swapped) return;
+        if (!join(saved, p->stream)) (void)hipStreamSynchronize(p->stream);
+        p->stream = saved;
+    }
+};
 
 template <typename T>
 static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp, const void* psi0, void* psi,
                           nlf_gs_stats* stats) {
+    SolveStream solve_stream(p, gp.graphs && !p->profiling);
     SolverWs* wp;
     NLF_TRY(solver_ws(p, &wp));
     SolverWs& w = *wp;
@@ -700,12 +804,8 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
                        (T*)w.rho, part_n, part_r, nb, 0);
     NLF_HIP(hipGetLastError());
 
-    int it = 0;
-    bool all_done = false;
-    int last_cg = 4;
-    std::vector<double> best_res(B, 1e300);
-    std::vector<int> stall(B, 0), stalled(B, 0);
-    for (it = 1; it <= max_iter && !all_done; ++it) {
+    // the three parts of an outer step; each only enqueues kernels
+    auto step_setup = [&]() -> int {
         NLF_TRY(potential(p, w.rho, w.pot));
         hipLaunchKernelGGL((k_gf_prep<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const T*)w.pot,
                            (const T*)w.phi, (T*)w.W, (V2<T>*)w.cw, part_mx, part_mn);
@@ -717,11 +817,11 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
                            (const V2<T>*)w.cw, (T*)w.x, (T*)w.r, (V2<T>*)w.cw, part_bb);
         hipLaunchKernelGGL(k_bb_final, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_bb, nb);
         NLF_HIP(hipGetLastError());
-        // convergence is read back first after about as many iterations as the previous solve took,
-        // then every second iteration (each read is a stream synchronisation)
-        int next_check = std::max(2, last_cg - 1);
-        int most = 0;
-        for (int cg = 0; cg < cg_max; ++cg) {
+        return NLF_OK;
+    };
+    // one inner iteration (fields whose solve converged skip the pointwise kernels)
+    auto cg_block = [&]() -> int {
+        {
             NLF_TRY(fft_full(p, w.cw, -1, B));
             hipLaunchKernelGGL((k_pcg_rz<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.cw, part_rz);
             hipLaunchKernelGGL((k_pcg_dir<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (V2<T>*)w.cw, (V2<T>*)w.ph,
@@ -733,6 +833,36 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
                                (const T*)w.Ap, (T*)w.x, (T*)w.r, (V2<T>*)w.cw, part_pap, part_rr, nb);
             hipLaunchKernelGGL(k_pcg_check, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_rr, nb);
             NLF_HIP(hipGetLastError());
+        }
+        return NLF_OK;
+    };
+    auto step_finish = [&]() -> int {
+        hipLaunchKernelGGL((k_norm2_part<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, part_n);
+        hipLaunchKernelGGL((k_normalize<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, (T*)w.phi,
+                           (T*)w.rho, part_n, part_r, nb, 1);
+        hipLaunchKernelGGL((k_residual_final<T>), dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_r, nb, eps0);
+        NLF_HIP(hipGetLastError());
+        return NLF_OK;
+    };
+    // Graphs are captured from the second outer step on (the first runs the launches directly,
+    // which also sets the kernels' LDS attributes); stage profiling needs direct launches.
+    StepGraph g_setup, g_cg, g_finish;
+    bool want_graphs = gp.graphs && !p->profiling;
+
+    int it = 0;
+    bool all_done = false;
+    int last_cg = 4;
+    std::vector<double> best_res(B, 1e300);
+    std::vector<int> stall(B, 0), stalled(B, 0);
+    for (it = 1; it <= max_iter && !all_done; ++it) {
+        bool graphs = want_graphs && it >= 2;
+        NLF_TRY(run_step(p, &graphs, g_setup, step_setup));
+        // convergence is read back first after about as many iterations as the previous solve took,
+        // then every second iteration (each read is a stream synchronisation)
+        int next_check = std::max(2, last_cg - 1);
+        int most = 0;
+        for (int cg = 0; cg < cg_max; ++cg) {
+            NLF_TRY(run_step(p, &graphs, g_cg, cg_block));
             if (cg + 1 >= next_check) {
                 NLF_TRY(read_flds(p, w, fh));
                 bool all = true;
@@ -745,11 +875,8 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
             }
         }
         last_cg = most;
-        hipLaunchKernelGGL((k_norm2_part<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, part_n);
-        hipLaunchKernelGGL((k_normalize<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.x, (T*)w.phi,
-                           (T*)w.rho, part_n, part_r, nb, 1);
-        hipLaunchKernelGGL((k_residual_final<T>), dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_r, nb, eps0, it);
-        NLF_HIP(hipGetLastError());
+        NLF_TRY(run_step(p, &graphs, g_finish, step_finish));
+        if (it >= 2 && !graphs) want_graphs = false;
         if (it % check_every == 0 || it == max_iter) {
             NLF_TRY(read_flds(p, w, fh));
             all_done = true;

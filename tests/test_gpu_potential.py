@@ -40,6 +40,11 @@ CASES = [
     ((32, 32, 32), (8.0, 8.0, 8.0), nlf.COULOMB3D, nlf.F64),
     ((32, 32, 32), (8.0, 8.0, 8.0), nlf.COULOMB3D, nlf.F32),
     ((16, 32, 8), (4.0, 8.0, 3.0), nlf.COULOMB3D, nlf.F64),
+    # 16 cells per axis: a 2 msp = 24 stencil wraps a 32-cell oversampled axis of two 16-cell
+    # gather tiles (it can start and end in the same tile)
+    ((16, 16), (4.0, 4.0), nlf.COULOMB2D, nlf.F64),
+    ((32, 16), (6.0, 4.0), nlf.LAPLACE2D, nlf.F32),
+    ((16, 16, 16), (4.0, 4.0, 4.0), nlf.COULOMB3D, nlf.F64),
 ]
 
 

@@ -141,6 +141,39 @@ def test_gs_mixed_schedule_reaches_fp64_tolerance():
     assert psi.dtype == torch.float32
 
 
+@pytest.mark.parametrize("prec,mixed", [(nlf.F64, False), (nlf.F32, True)])
+def test_gs_graph_replay_matches_direct_launches(prec, mixed):
+    """Each outer step captured once as HIP graphs and replayed (hundreds of replays, with host
+    convergence reads and direct potential evaluations between them) gives the same flow as
+    launching every kernel directly: step counts, energies and states agree up to the summation
+    order of the spreading's floating-point atomics.  A second solve on the same plan captures
+    new graphs and reproduces the first."""
+    print(f"[gs graph] prec={prec} mixed={mixed}", flush=True)
+    n, L = (64, 64), (8.0, 8.0)
+    plan = nlf.Plan(n, L, nlf.COULOMB2D, prec=prec, batch=3)
+    betas = [5.0, 50.0, -3.0]
+    gams = [(1.0, 2.0), (1.5, 1.0), (1.0, 1.0)]
+    kw = dict(tau=0.5, eps0=1e-10, mixed=mixed)
+    psi_g, st_g, s_g = plan.ground_state(betas, gams, graph=True, **kw)
+    rho = torch.tensor(np.stack([inputs.gaussian(n, L)] * 3), dtype=plan.rdtype, device="cuda")
+    u_between = plan.potential(rho).clone()
+    psi_d, st_d, s_d = plan.ground_state(betas, gams, graph=False, **kw)
+    assert s_g == nlf.OK and s_d == nlf.OK
+    tol = 1e-9 if prec == nlf.F64 else 2e-6
+    for a, b in zip(st_g, st_d):
+        assert abs(a["iters"] - b["iters"]) <= 2, (a["iters"], b["iters"])
+        for key in ("E", "mu", "Ekin", "Epot", "Eint"):
+            assert abs(a[key] - b[key]) < 1e-10 * max(1.0, abs(b[key])), key
+    assert rel_err(psi_g.cpu().numpy().astype(np.float64), psi_d.cpu().numpy().astype(np.float64)) < tol
+    psi_g2, st_g2, s_g2 = plan.ground_state(betas, gams, graph=True, **kw)
+    assert s_g2 == nlf.OK
+    assert rel_err(psi_g2.cpu().numpy().astype(np.float64), psi_g.cpu().numpy().astype(np.float64)) < tol
+    # the plan's potential is untouched by the captured solves
+    # (FP32 plans add their spreading sums with FP32 atomics, whose order varies between calls)
+    tol_u = 1e-12 if prec == nlf.F64 else 1e-6
+    assert rel_err(plan.potential(rho).cpu().numpy(), u_between.cpu().numpy()) < tol_u
+
+
 def test_gs_batch_over_plans_of_uneven_size():
     """nlf_ground_state_batch: two grid sizes, two fields each, solved concurrently on separate
     streams; every field equals its individual solve."""
