@@ -36,6 +36,9 @@ template <typename T> struct FftCfg;
 template <> struct FftCfg<double> { static constexpr int E = 8192, NT = 512; };
 template <> struct FftCfg<float>  { static constexpr int E = 16384, NT = 1024; };
 struct RowCfg { static constexpr int E = 2048, NT = 256; };
+// Strided-axis kernel for short columns (n <= 512): a quarter of the LDS and half the threads of
+// FftCfg, so that several workgroups share a CU.
+struct ColSmallCfg { static constexpr int E = 4096, NT = 256; };
 
 // data index j (0..nd-1, x_j = -L + j h) -> row of the 2x oversampled periodic grid holding
 // centred frequency/position j - nd/2
@@ -270,11 +273,10 @@ struct ColsArgs {
     const void* tw;
 };
 
-template <typename T, int DIR, bool LPRUNE, bool SPRUNE>
-__global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_cols(ColsArgs a) {
+template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E>
+__global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    constexpr int NT = FftCfg<T>::NT;
     const int n = a.n, C = a.C;
     const int pitch = n + 1;
     // XCD-aware order: consecutive hardware workgroup ids go round-robin over the 8 XCDs; give
@@ -293,7 +295,7 @@ __global__ void __launch_bounds__(FftCfg<T>::NT) k_fft_cols(ColsArgs a) {
         buf[c * pitch + r] = v;
     }
     __syncthreads();
-    lds_fft<T, DIR, NT, FftCfg<T>::E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
         if (!SPRUNE || is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
@@ -333,9 +335,8 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     return NLF_OK;
 }
 
-template <typename T, int DIR, bool LP, bool SP>
-static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
-    constexpr int E = FftCfg<T>::E, NT = FftCfg<T>::NT;
+template <typename T, int DIR, bool LP, bool SP, int NT, int E>
+static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     a.lg = ilog2(a.n);
     int C = 16;
     while (C > 1 && (C * (a.n + 1) > E || a.inner % C)) C >>= 1;
@@ -346,13 +347,20 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
     size_t lds = (size_t)C * (a.n + 1) * sizeof(V2<T>);
     static bool attr_set = false;
     if (!attr_set) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP>,
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP, NT, E>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP>), grid, dim3(NT), lds, p->stream, a);
+    hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP, NT, E>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
+}
+
+template <typename T, int DIR, bool LP, bool SP>
+static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
+    if (a.n <= 512)
+        return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E>(p, a, outer, batch);
+    return launch_cols_cfg<T, DIR, LP, SP, FftCfg<T>::NT, FftCfg<T>::E>(p, a, outer, batch);
 }
 
 template <typename T>

@@ -290,12 +290,16 @@ __global__ void k_pcg_init(Geo g, Fld* fl, const T* phi, const T* W, const V2<T>
     const int b = blockIdx.y;
     if (fl[b].done) return;
     const double tau = fl[b].tau;
+    // Start from c phi^n with c = |x| of the previous step's solution (~ 1/(1 + tau mu) for the
+    // current chemical potential mu): r0 = (1 - c) phi/tau - c H phi = c (mu phi - H phi), the
+    // eigen-residual, which vanishes as the flow converges.  The first step starts from phi^n.
+    const double c = (fl[b].steps > 0 && fl[b].norm2 > 0.0) ? sqrt(fl[b].norm2) : 1.0;
     double s = 0;
     for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
         long long k = (long long)b * g.N + i;
         double p = (double)phi[k];
-        double ri = -((double)kphi[k].x + (double)W[k] * p);
-        x[k] = phi[k];
+        double ri = (1.0 - c) * p / tau - c * ((double)kphi[k].x + (double)W[k] * p);
+        x[k] = (T)(c * p);
         r[k] = (T)ri;
         cw[k] = mkc<T>((T)ri, (T)0);
         s += (p / tau) * (p / tau);
@@ -657,7 +661,7 @@ static GsParams gs_params(const nlf_plan* p, const nlf_gf_opts* gf) {
     g.cg_tol = (gf && gf->cg_tol > 0) ? gf->cg_tol : (p->prec == NLF_F64 ? 1e-13 : 1e-6);
     g.cg_max = (gf && gf->cg_max_iter > 0) ? gf->cg_max_iter : 200;
     g.stall_stop = 0;
-    g.graphs = !(gf && gf->no_graph);
+    g.graphs = (gf && gf->graph) ? 1 : 0;
     return g;
 }
 

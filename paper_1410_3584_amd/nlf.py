@@ -52,7 +52,7 @@ class Phys(ctypes.Structure):
 class GfOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("eps0", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int),
-                ("mixed", ctypes.c_int), ("eps_switch", ctypes.c_double), ("no_graph", ctypes.c_int)]
+                ("mixed", ctypes.c_int), ("eps_switch", ctypes.c_double), ("graph", ctypes.c_int)]
 
 
 class GsStats(ctypes.Structure):
@@ -250,13 +250,13 @@ class Plan:
 
     def ground_state(self, beta, gamma, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
                      cg_tol=0.0, cg_max_iter=0, psi0=None, V=None, out=None, mixed=False, eps_switch=0.0,
-                     graph=True):
+                     graph=False):
         """nlf_ground_state; returns (psi, [stats dict per field], status)."""
         phys = self._phys(beta, gamma, V)
         if V is not None:
             self._check_in(V, self.torch.float64, int(np.prod(self.n)))
         gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch,
-                    0 if graph else 1)
+                    1 if graph else 0)
         N = int(np.prod(self.n)) * self.batch
         if psi0 is not None:
             self._check_in(psi0, self.rdtype, N)
@@ -286,7 +286,7 @@ class Plan:
 
 
 def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
-                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=True):
+                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=False):
     """nlf_ground_state_batch over several plans (one per grid size); betas[i] / gammas[i] give
     the per-field parameters of plan i.  Returns ([psi_i], [[stats]], status)."""
     import torch
@@ -301,7 +301,7 @@ def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=1000
     st_keep = [(GsStats * p.batch)() for p in plans]
     stats = (ctypes.POINTER(GsStats) * k)(*[ctypes.cast(a, ctypes.POINTER(GsStats)) for a in st_keep])
     gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch,
-                    0 if graph else 1)
+                    1 if graph else 0)
     status = lib.nlf_ground_state_batch(k, hs, phys, ctypes.byref(gf), psi0, psi, stats)
     if status not in (OK, ENOCONV):
         _check(status)
@@ -379,11 +379,11 @@ class Model:
         return out
 
     def ground_state(self, plan, betas, gammas, coarse_n, tau=1e-2, eps0=1e-10, max_iter=100000,
-                     check_every=10, cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=True):
+                     check_every=10, cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=False):
         """nlf_ws_ground_state; returns (psi, [stats], status, used flags)."""
         phys = plan._phys(betas, gammas, None)
         gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch,
-                    0 if graph else 1)
+                    1 if graph else 0)
         out = self.torch.empty(plan._shape(), dtype=plan.rdtype, device="cuda")
         stats = (GsStats * plan.batch)()
         used = (ctypes.c_int * plan.batch)()

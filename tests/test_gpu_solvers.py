@@ -174,15 +174,18 @@ def test_gs_graph_replay_matches_direct_launches(prec, mixed):
     assert rel_err(plan.potential(rho).cpu().numpy(), u_between.cpu().numpy()) < tol_u
 
 
-def test_gs_batch_over_plans_of_uneven_size():
+@pytest.mark.parametrize("graph", [False, True])
+def test_gs_batch_over_plans_of_uneven_size(graph):
     """nlf_ground_state_batch: two grid sizes, two fields each, solved concurrently on separate
-    streams; every field equals its individual solve."""
+    streams (each thread capturing its own step graphs when graph=True); every field equals its
+    individual solve."""
+    print(f"[gs batch over plans] graph={graph}", flush=True)
     sizes = [(64, 64), (128, 128)]
     betas = [[3.0, 30.0], [10.0, 1.0]]
     gams = [[(1.0, 1.0), (1.0, 1.5)], [(1.0, 0.7), (1.0, 1.2)]]
     streams = [torch.cuda.Stream() for _ in sizes]
     plans = [nlf.Plan(n, (16.0, 16.0), nlf.COULOMB2D, batch=2, stream=s.cuda_stream) for n, s in zip(sizes, streams)]
-    outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.5, eps0=1e-10)
+    outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.5, eps0=1e-10, graph=graph)
     assert status == nlf.OK
     for i, n in enumerate(sizes):
         for j in range(2):
