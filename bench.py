@@ -171,6 +171,7 @@ def ground_states_per_s(torch, nlf, inputs):
              for k, s in zip(keys, streams)]
     betas = [[d["beta"] for d in groups[k]] for k in keys]
     gams = [[d["gamma"] for d in groups[k]] for k in keys]
+    tuned = {str(k): p.autotune(reps=5)[0] for k, p in zip(keys, plans)}   # spreading decomposition per size
     kw = dict(tau=0.25, eps0=1e-10, max_iter=5000, mixed=True)
     nlf.ground_state_batch(plans, betas, gams, **kw)          # warm-up (twin plans, workspaces)
     torch.cuda.synchronize()
@@ -184,7 +185,9 @@ def ground_states_per_s(torch, nlf, inputs):
             "max_residual": max(s["residual"] for s in flat),
             "mean_outer_iters": float(np.mean([s["iters"] for s in flat])),
             "mean_fp32_iters": float(np.mean([s["iters_fp32"] for s in flat])),
-            "sizes": {str(k): len(groups[k]) for k in keys}}
+            "sizes": {str(k): len(groups[k]) for k in keys},
+            "spread_autotuned": {k: {"mode": "gather" if v[0] == 0 else "scatter", "block": v[1], "item": v[2]}
+                                 for k, v in tuned.items()}}
 
 
 def main():

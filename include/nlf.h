@@ -90,6 +90,11 @@ typedef struct {
     long long n_nodes;     /* M = n_r n_theta n_phi (3D) or n_r n_phi (2D), the full node set  */
     long long n_half;      /* M / 2 nodes actually evaluated (the other half by symmetry)      */
     long long workspace_bytes;
+    /* spreading work decomposition in use (see nlf_plan_set_spread / nlf_plan_autotune) */
+    int spread_mode;       /* NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER                       */
+    int spread_block;      /* candidates per block of the gather kernel (64 or 128)         */
+    int spread_item;       /* candidates per work item of the gather kernel (256 .. 2048)   */
+    int gather_available;  /* 1 if the plan built its gather-tile candidate lists           */
 } nlf_plan_info;
 
 /* Create a plan for the potential of `kernel` on `box` (Sec. 2.1 nodes and weights, Eq.
@@ -100,6 +105,23 @@ int nlf_plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* 
                     nlf_plan** out);
 int nlf_plan_destroy(nlf_plan* plan);
 int nlf_plan_get_info(const nlf_plan* plan, nlf_plan_info* info);
+
+/* ---- spreading work decomposition (project addition, not in the paper) -----------------------
+ * NLF_SPREAD_GATHER: every gather tile of the oversampled grid (8 x 16 cells in 2D, 8 x 4 x 4 in
+ *   3D) sums its candidate nodes as matrix products, in work items of `item` candidates taken
+ *   `block` at a time, one atomic per cell and item.
+ * NLF_SPREAD_SCATTER: each node adds its stencil into an LDS window of its bin (LDS atomics),
+ *   then the window into the grid.
+ * nlf_plan_set_spread selects one (block 64 or 128; item 256, 512, 1024 or 2048; GATHER needs
+ * the plan's candidate lists, info.gather_available; SCATTER is not available to FP32 3D plans,
+ * which spread into an FP64 grid); returns NLF_EINVAL otherwise.
+ * nlf_plan_autotune times every decomposition the plan supports on its own buffers (node values
+ * set to 1, `reps` timed calls each, default 5 if reps <= 0), keeps the fastest and returns
+ * its time per call in *best_ms (may be NULL).  Results are the same up to the summation order
+ * of floating-point atomics.  Synchronises the plan's stream.                               */
+enum { NLF_SPREAD_GATHER = 0, NLF_SPREAD_SCATTER = 1 };
+int nlf_plan_set_spread(nlf_plan* plan, int mode, int block, int item);
+int nlf_plan_autotune(nlf_plan* plan, int reps, double* best_ms);
 
 /* Quadrature nodes of the plan in canonical order (radial index slowest, then polar in 3D,
  * then azimuth fastest): k_host receives M*dim doubles (k_m components in grid-axis order),

@@ -97,6 +97,13 @@ struct nlf_plan {
     nlf::GItem* gitems = nullptr;
     int ngitems = 0;
     double* iacc = nullptr;     // [batch][Mh] complex FP64: tile-gathered interpolation sums
+    // spreading work decomposition (nlf_plan_set_spread / nlf_plan_autotune)
+    int spread_mode = 0;        // NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER
+    int spread_kc = 64;         // candidates per block of the gather kernel
+    int item_cap = nlf::kMItem; // candidates per work item
+    std::vector<long long> gtile_off;   // per gather tile: first candidate (ntiles + 1 entries)
+    int gng[3] = {1, 1, 1};     // gather tiles per axis
+    long long gitems_cap = 0;   // GItem slots allocated on the device
     double* dec[3] = {nullptr, nullptr, nullptr};   // 1 / c_g(j - n/2), length n_i
     void* tw_big[3] = {nullptr, nullptr, nullptr};  // twiddles of length Mr_i (plan precision)
     void* tw_small[3] = {nullptr, nullptr, nullptr};// twiddles of length n_i (solver FFTs)
@@ -138,6 +145,7 @@ int fft_type2_forward(nlf_plan* p, const void* rho);          // rho -> grid_a (
 int fft_type1_inverse(nlf_plan* p, void* u, bool add_u1);     // grid_b -> u (pruned, fused postcorrect)
 int fft_full(nlf_plan* p, void* data, int dir, int batch);    // n-grid complex FFT in place, all axes
 int fill_zero(nlf_plan* p, void* ptr, size_t bytes);
+int set_items(nlf_plan* p, int cap);                          // rebuild the gather work items
 
 // NUFFT stages (nufft.hip)
 int moments(nlf_plan* p, const void* rho);

@@ -31,8 +31,6 @@ template <> __device__ __forceinline__ double2 mk2<double>(double x, double y) {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-// candidates per block of the tile-gathered spreading (two threads per candidate)
-constexpr int kSpreadBlock = 64;
 
 // index modulo an oversampled grid extent (always a power of two)
 __device__ __forceinline__ int wrap(int v, int M) { return v & (M - 1); }
@@ -763,6 +761,12 @@ __global__ void k_iepilogue(const double2* __restrict__ acc, long long astride, 
     }
 }
 
+template <typename T>
+__global__ void k_fill_one(V2<T>* c, long long count) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        c[i] = mk2<T>((T)1, (T)0);
+}
+
 // ---- fold of a caller-supplied full node vector (type-1 stage entry) ---------------------------
 // Re sum_all c_m e^{ikx} = Re sum_half (c_m + conj(c_{-m})) e^{ikx}
 template <typename T>
@@ -888,28 +892,35 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea) {
     return NLF_OK;
 }
 
-template <typename T, int MSP>
-static int spread_t(nlf_plan* p) {
+template <typename T, int MSP, int KC>
+static int gather_spread_t(nlf_plan* p) {
     NodeArgs na = node_args(p);
     V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
     const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
-    if (p->use_gather) {
-        dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
-        const double qq = exp(-2.0 * p->gc.alpha);
-        if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid (3D)
-            double2* g64 = reinterpret_cast<double2*>(p->grid_b);
-            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, kSpreadBlock>), ggrid, dim3(2 * kSpreadBlock), 0, p->stream, g64, p->G, c,
-                               p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
-        } else if (p->dim == 2) {
-            hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, kSpreadBlock>), ggrid, dim3(2 * kSpreadBlock), 0, p->stream, g, p->G, c, p->Mh,
-                               na, p->gitems, p->ngitems, p->gcand, qq);
-        } else {
-            hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, kSpreadBlock>), ggrid, dim3(2 * kSpreadBlock), 0, p->stream, g, p->G, c, p->Mh,
-                               na, p->gitems, p->ngitems, p->gcand, qq);
-        }
-        NLF_HIP(hipGetLastError());
-        return NLF_OK;
+    dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
+    const double qq = exp(-2.0 * p->gc.alpha);
+    if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid (3D)
+        double2* g64 = reinterpret_cast<double2*>(p->grid_b);
+        hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G, c,
+                           p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+    } else if (p->dim == 2) {
+        hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh, na,
+                           p->gitems, p->ngitems, p->gcand, qq);
+    } else {
+        hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, KC>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh, na,
+                           p->gitems, p->ngitems, p->gcand, qq);
     }
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+template <typename T, int MSP>
+static int spread_t(nlf_plan* p) {
+    if (p->use_gather && p->spread_mode == NLF_SPREAD_GATHER)
+        return p->spread_kc == 128 ? gather_spread_t<T, MSP, 128>(p) : gather_spread_t<T, MSP, 64>(p);
+    NodeArgs na = node_args(p);
+    V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
+    const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
     dim3 grid(grid_chunks(p), p->batch);
     if (p->dim == 2)
         hipLaunchKernelGGL((k_spread2<T, MSP>), grid, dim3(kChunk), window_bytes(p), p->stream, g, p->G, c, p->Mh, na);
@@ -1047,6 +1058,83 @@ int nlf_type1(nlf_plan* p, const void* c, void* u) {
     NLF_TRY(fold_c(p, c));
     NLF_TRY(spread(p));
     return fft_type1_inverse(p, u, false);
+}
+
+int nlf_plan_set_spread(nlf_plan* p, int mode, int block, int item) {
+    clear_error();
+    if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (mode != NLF_SPREAD_GATHER && mode != NLF_SPREAD_SCATTER)
+        return set_error(NLF_EINVAL, "spread mode must be NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER");
+    if (mode == NLF_SPREAD_SCATTER) {
+        // the scatter kernels accumulate in the plan's precision; FP32 3D plans keep an FP64
+        // spreading grid for the gather kernels (the FP32 bar needs it)
+        if (p->t1_prec != p->prec)
+            return set_error(NLF_EINVAL, "this plan spreads into an FP64 grid: only NLF_SPREAD_GATHER");
+        p->spread_mode = mode;
+        return NLF_OK;
+    }
+    if (!p->use_gather) return set_error(NLF_EINVAL, "this plan has no gather-tile candidate lists");
+    if (block != 64 && block != 128) return set_error(NLF_EINVAL, "block must be 64 or 128");
+    if (item != 256 && item != 512 && item != 1024 && item != 2048)
+        return set_error(NLF_EINVAL, "item must be 256, 512, 1024 or 2048");
+    if (item != p->item_cap) NLF_TRY(set_items(p, item));
+    p->spread_mode = mode;
+    p->spread_kc = block;
+    return NLF_OK;
+}
+
+int nlf_plan_autotune(nlf_plan* p, int reps, double* best_ms) {
+    clear_error();
+    if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (reps <= 0) reps = 5;
+    struct Cfg { int mode, block, item; };
+    std::vector<Cfg> cfgs;
+    if (p->use_gather)
+        for (int block : {64, 128})
+            for (int item : {256, 512, 1024, 2048}) cfgs.push_back({NLF_SPREAD_GATHER, block, item});
+    if (p->t1_prec == p->prec) cfgs.push_back({NLF_SPREAD_SCATTER, p->spread_kc, p->item_cap});
+    if (cfgs.empty()) return set_error(NLF_EINVAL, "no spreading decomposition to time");
+    // node values 1: every tile the candidates reach receives a nonzero sum
+    const long long nv = (long long)p->batch * p->Mh;
+    if (p->prec == NLF_F64)
+        hipLaunchKernelGGL((k_fill_one<double>), dim3((unsigned)std::min<long long>((nv + 255) / 256, 65535)), dim3(256),
+                           0, p->stream, (double2*)p->cbuf, nv);
+    else
+        hipLaunchKernelGGL((k_fill_one<float>), dim3((unsigned)std::min<long long>((nv + 255) / 256, 65535)), dim3(256),
+                           0, p->stream, (float2*)p->cbuf, nv);
+    NLF_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    NLF_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return set_error(NLF_EHIP, "hipEventCreate failed");
+    }
+    double best = 1e300;
+    Cfg bc = cfgs.front();
+    int rc = NLF_OK;
+    for (const Cfg& c : cfgs) {
+        if ((rc = nlf_plan_set_spread(p, c.mode, c.block, c.item)) != NLF_OK) break;
+        if ((rc = spread_only(p)) != NLF_OK) break;   // warm-up
+        if (hipEventRecord(e0, p->stream) != hipSuccess) { rc = set_error(NLF_EHIP, "hipEventRecord failed"); break; }
+        for (int r = 0; r < reps && rc == NLF_OK; ++r) rc = spread_only(p);
+        if (rc != NLF_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = set_error(NLF_EHIP, "timing the spreading failed");
+            break;
+        }
+        if (ms / reps < best) {
+            best = ms / reps;
+            bc = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NLF_OK) return rc;
+    NLF_TRY(nlf_plan_set_spread(p, bc.mode, bc.block, bc.item));
+    if (best_ms) *best_ms = best;
+    return NLF_OK;
 }
 
 }  // extern "C"

@@ -24,6 +24,34 @@ void clear_error() { g_err[0] = 0; }
 
 size_t elem_size(int prec) { return prec == NLF_F64 ? 16 : 8; }
 
+// Work items of the gather kernels: the candidates of each tile cut into pieces of <= cap.
+int set_items(nlf_plan* p, int cap) {
+    std::vector<GItem> items;
+    const long long ntiles = (long long)p->gng[0] * p->gng[1] * p->gng[2];
+    for (long long t = 0; t < ntiles; ++t) {
+        const long long beg = p->gtile_off[t], end = p->gtile_off[t + 1];
+        const int g2 = (int)(t % p->gng[2]);
+        const int g1 = (int)((t / p->gng[2]) % p->gng[1]);
+        const int g0 = (int)(t / ((long long)p->gng[2] * p->gng[1]));
+        for (long long s0 = beg; s0 < end; s0 += cap) {
+            GItem it;
+            it.g0 = g0;
+            it.g1 = g1;
+            it.g2 = g2;
+            it.count = (int)std::min<long long>(cap, end - s0);
+            it.start = s0;
+            items.push_back(it);
+        }
+    }
+    if ((long long)items.size() > p->gitems_cap)
+        return set_error(NLF_EINVAL, "work-item size %d below the allocated minimum", cap);
+    NLF_HIP(hipStreamSynchronize(p->stream));   // no kernel of the plan may still read the items
+    if (!items.empty()) NLF_HIP(hipMemcpy(p->gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice));
+    p->ngitems = (int)items.size();
+    p->item_cap = cap;
+    return NLF_OK;
+}
+
 int dev_alloc(nlf_plan* p, void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) bytes = 256;
@@ -363,26 +391,18 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
                             cand[pos[tid]++] = (int)j;
                         }
             }
-            std::vector<GItem> items;
-            for (long long t = 0; t < ntiles; ++t) {
-                long long beg = tcount[t], end = tcount[t + 1];
-                int g2 = (int)(t % ng[2]);
-                int g1 = (int)((t / ng[2]) % ng[1]);
-                int g0 = (int)(t / ((long long)ng[2] * ng[1]));
-                for (long long s0 = beg; s0 < end; s0 += kMItem) {
-                    GItem it;
-                    it.g0 = g0;
-                    it.g1 = g1;
-                    it.g2 = g2;
-                    it.count = (int)std::min<long long>(kMItem, end - s0);
-                    it.start = s0;
-                    items.push_back(it);
-                }
-            }
-            p->ngitems = (int)items.size();
+            p->gtile_off.assign(tcount.begin(), tcount.end());
+            for (int i = 0; i < 3; ++i) p->gng[i] = ng[i];
             p->use_gather = 1;
             NLF_TRY(upload(p, (void**)&p->gcand, cand.data(), std::max<size_t>(1, cand.size()) * sizeof(int)));
-            NLF_TRY(upload(p, (void**)&p->gitems, items.data(), std::max<size_t>(1, items.size()) * sizeof(GItem)));
+            // room for the finest item size the decomposition allows (256 candidates)
+            long long most = 0;
+            for (long long t = 0; t < ntiles; ++t) most += (tcount[t + 1] - tcount[t] + 255) / 256;
+            p->gitems_cap = std::max(1LL, most);
+            NLF_TRY(dev_alloc(p, (void**)&p->gitems, (size_t)p->gitems_cap * sizeof(GItem)));
+            // default work items: 512 candidates for the wide FP64 stencils, 256 for narrower ones
+            // (the fastest on the 2D workloads measured; nlf_plan_autotune picks per plan)
+            NLF_TRY(set_items(p, p->msp >= 10 ? 512 : 256));
         }
     }
 
@@ -602,6 +622,10 @@ int nlf_plan_get_info(const nlf_plan* p, nlf_plan_info* info) {
     info->n_nodes = p->M;
     info->n_half = p->Mh;
     info->workspace_bytes = p->workspace_bytes;
+    info->spread_mode = (p->use_gather && p->spread_mode == NLF_SPREAD_GATHER) ? NLF_SPREAD_GATHER : NLF_SPREAD_SCATTER;
+    info->spread_block = p->spread_kc;
+    info->spread_item = p->item_cap;
+    info->gather_available = p->use_gather;
     return NLF_OK;
 }
 

@@ -22,8 +22,9 @@ EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan
            "nlf_last_error", "nlf_strerror", "nlf_version", "nlf_plan_set_profiling",
            "nlf_plan_stage_times", "nlf_ws_create", "nlf_ws_destroy", "nlf_ws_num_params", "nlf_ws_params",
            "nlf_ws_set_standardisation", "nlf_ws_forward", "nlf_ws_loss_grad", "nlf_ws_train",
-           "nlf_ws_predict", "nlf_ws_ground_state"]
+           "nlf_ws_predict", "nlf_ws_ground_state", "nlf_plan_set_spread", "nlf_plan_autotune"]
 STAGES = ["moments", "fft_fwd", "interp", "zero", "spread", "fft_inv"]
+SPREAD_GATHER, SPREAD_SCATTER = 0, 1
 
 
 class Box(ctypes.Structure):
@@ -42,7 +43,9 @@ class PlanInfo(ctypes.Structure):
                 ("L", ctypes.c_double * 3), ("h", ctypes.c_double * 3), ("P", ctypes.c_double),
                 ("sigma", ctypes.c_double), ("n_grid", ctypes.c_longlong),
                 ("n_nodes", ctypes.c_longlong), ("n_half", ctypes.c_longlong),
-                ("workspace_bytes", ctypes.c_longlong)]
+                ("workspace_bytes", ctypes.c_longlong), ("spread_mode", ctypes.c_int),
+                ("spread_block", ctypes.c_int), ("spread_item", ctypes.c_int),
+                ("gather_available", ctypes.c_int)]
 
 
 class Phys(ctypes.Structure):
@@ -99,6 +102,8 @@ def load(path=LIB_PATH):
                                            ctypes.POINTER(GfOpts), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                            ctypes.POINTER(ctypes.POINTER(GsStats))]
     lib.nlf_plan_set_profiling.argtypes = [vp, ip]
+    lib.nlf_plan_set_spread.argtypes = [vp, ip, ip, ip]
+    lib.nlf_plan_autotune.argtypes = [vp, ip, dp]
     lib.nlf_plan_stage_times.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong), ip]
     fp = ctypes.POINTER(ctypes.c_float)
     lib.nlf_ws_create.argtypes = [ip, ip, ip, ctypes.c_ulonglong, vp, ctypes.POINTER(vp)]
@@ -192,6 +197,28 @@ class Plan:
 
     def set_profiling(self, on):
         _check(load().nlf_plan_set_profiling(self._h, 1 if on else 0))
+
+    def _refresh_info(self):
+        info = PlanInfo()
+        _check(load().nlf_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+        return info
+
+    def spread_config(self):
+        """(mode, block, item) of the spreading work decomposition in use."""
+        i = self._refresh_info()
+        return i.spread_mode, i.spread_block, i.spread_item
+
+    def set_spread(self, mode, block=64, item=1024):
+        """nlf_plan_set_spread: mode SPREAD_GATHER or SPREAD_SCATTER."""
+        _check(load().nlf_plan_set_spread(self._h, int(mode), int(block), int(item)))
+        return self.spread_config()
+
+    def autotune(self, reps=5):
+        """nlf_plan_autotune; returns ((mode, block, item), best ms per spreading call)."""
+        ms = ctypes.c_double()
+        _check(load().nlf_plan_autotune(self._h, int(reps), ctypes.byref(ms)))
+        return self.spread_config(), ms.value
 
     def stage_times(self, reset=True):
         """{stage: (total ms, launches)} since the last reset (synchronises the plan's stream)."""

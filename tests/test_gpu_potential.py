@@ -84,6 +84,42 @@ def test_type1_parity(n, L, kernel, prec):
     assert rel_err(got, want) <= TOL[prec]
 
 
+@pytest.mark.parametrize("n,L,kernel,prec", [CASES[0], CASES[2], CASES[8], CASES[9]])
+def test_spread_decompositions_and_autotune(n, L, kernel, prec):
+    """Every spreading work decomposition (gather blocks of 64/128 candidates x work items of
+    256..2048 candidates, and the LDS-atomic scatter) gives the oracle's type-1 sum; the
+    autotuner times them all, keeps one of them, and the plan still agrees with the oracle."""
+    print(f"[spread decompositions] n={n} kernel={kernel} prec={prec}", flush=True)
+    plan = nlf.Plan(n, L, kernel, prec=prec)
+    assert plan.info.gather_available == 1
+    k, _ = plan.nodes()
+    rng = np.random.default_rng(7)
+    c = (rng.normal(size=len(k)) + 1j * rng.normal(size=len(k))) / len(k)
+    cd = torch.tensor(c, dtype=plan.cdtype, device="cuda")
+    want = op.type1_direct(cd.cpu().numpy().astype(np.complex128), n, L, k)
+    cfgs = [(nlf.SPREAD_GATHER, b, i) for b in (64, 128) for i in (256, 512, 1024, 2048)]
+    if len(n) == 3 and prec == nlf.F32:
+        # FP32 3D plans spread into an FP64 grid, which only the gather kernels fill
+        with pytest.raises(nlf.NlfError):
+            plan.set_spread(nlf.SPREAD_SCATTER)
+    else:
+        cfgs.append((nlf.SPREAD_SCATTER, 64, 1024))
+    for mode, block, item in cfgs:
+        got_cfg = plan.set_spread(mode, block, item)
+        assert got_cfg[0] == mode
+        got = plan.type1(cd).cpu().numpy().astype(np.float64)
+        assert rel_err(got, want) <= TOL[prec], (mode, block, item)
+    best, ms = plan.autotune(reps=2)
+    assert ms > 0.0
+    assert best in cfgs or (best[0] == nlf.SPREAD_SCATTER and any(c[0] == best[0] for c in cfgs))
+    got = plan.type1(cd).cpu().numpy().astype(np.float64)
+    assert rel_err(got, want) <= TOL[prec]
+    with pytest.raises(nlf.NlfError):
+        plan.set_spread(nlf.SPREAD_GATHER, 96, 1024)
+    with pytest.raises(nlf.NlfError):
+        plan.set_spread(nlf.SPREAD_GATHER, 64, 300)
+
+
 def test_batch_matches_single():
     n, L = (64, 64), (8.0, 8.0)
     rhos = np.stack([_case_density(n, L, s) for s in (1, 2, 3)])
