@@ -113,8 +113,8 @@ int nlf_plan_get_info(const nlf_plan* plan, nlf_plan_info* info);
  * NLF_SPREAD_SCATTER: each node adds its stencil into an LDS window of its bin (LDS atomics),
  *   then the window into the grid.
  * nlf_plan_set_spread selects one (block 64 or 128; item 256, 512, 1024 or 2048; GATHER needs
- * the plan's candidate lists, info.gather_available; SCATTER is not available to FP32 3D plans,
- * which spread into an FP64 grid); returns NLF_EINVAL otherwise.
+ * the plan's candidate lists, info.gather_available; SCATTER is not available to FP32 plans with
+ * candidate lists, which spread into an FP64 grid); returns NLF_EINVAL otherwise.
  * nlf_plan_autotune times every decomposition the plan supports on its own buffers (node values
  * set to 1, `reps` timed calls each, default 5 if reps <= 0), keeps the fastest and returns
  * its time per call in *best_ms (may be NULL).  Results are the same up to the summation order
@@ -150,7 +150,8 @@ int nlf_type1(nlf_plan* plan, const void* c_dev, void* u_dev);
  * milliseconds and the number of timed launches of each stage since the last reset, and resets
  * the accumulators if `reset` is non-zero.  ms and counts are host arrays of NLF_NSTAGES entries
  * (either may be NULL).                                                                         */
-#define NLF_STAGE_MOMENTS   0   /* FP64 moments of rho (Laplace kernel only)                       */
+#define NLF_STAGE_MOMENTS   0   /* the FP64 moments of rho (Laplace kernel) are summed inside the
+                                 * forward FFT passes; this stage reports 0                      */
 #define NLF_STAGE_FFT_FWD   1   /* precorrect + pad + forward FFT of the oversampled grid          */
 #define NLF_STAGE_INTERP    2   /* Gaussian interpolation to the nodes + symbol x weight           */
 #define NLF_STAGE_ZERO      3   /* clearing the spreading grid                                     */

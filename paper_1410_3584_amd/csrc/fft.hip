@@ -159,9 +159,23 @@ struct RowsArgs {
     const double* mom;     // [batch][4]: m0, m1x, m1y
     const double* u11;     // [N]: u_{1,1} on the grid
     double sigma, L0, L1, h0, h1;
+    // LOAD_RHO, 2D Laplace: per-workgroup partial sums of rho, x rho, y rho ([batch][grid.x][3])
+    double* mom_part;
 };
 
-template <typename T, typename TIO, int DIR, int LOAD, int STORE>
+// sum of v over the workgroup (blockDim.x a multiple of 64, <= 1024); every thread gets it
+__device__ __forceinline__ double wg_sum(double v, double* sh16) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh16[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += sh16[i];
+    return s;
+}
+
+template <typename T, typename TIO, int DIR, int LOAD, int STORE, int E>
 __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
@@ -195,6 +209,7 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     // ---- load
     if (LOAD == LOAD_RHO) {
         const TIO* rho = reinterpret_cast<const TIO*>(a.rho) + (long long)b * a.rstride;
+        double m0 = 0.0, mx = 0.0, my = 0.0;   // moments of the rows read (2D Laplace)
         for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
             int l = idx / n, c = idx - l * n;
             double fac = 1;
@@ -205,9 +220,27 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
             if (is_data_row(c, ndl, n)) {
                 int j = (c < ndl / 2) ? c + ndl / 2 : c - (n - ndl / 2);
                 long long src = (long long)(line0 + l) * ndl + j;
-                v.x = (T)((double)rho[src] * fac * decl[j]);
+                const double rv = (double)rho[src];
+                v.x = (T)(rv * fac * decl[j]);
+                if (a.mom_part) {
+                    m0 += rv;
+                    mx += rv * (-a.L0 + (line0 + l) * a.h0);
+                    my += rv * (-a.L1 + j * a.h1);
+                }
             }
             buf[l * pitch + c] = v;
+        }
+        if (a.mom_part) {   // uniform over the workgroup
+            __shared__ double red16[16];
+            m0 = wg_sum(m0, red16);
+            mx = wg_sum(mx, red16);
+            my = wg_sum(my, red16);
+            if (threadIdx.x == 0) {
+                double* o = a.mom_part + ((long long)b * gridDim.x + blockIdx.x) * 3;
+                o[0] = m0;
+                o[1] = mx;
+                o[2] = my;
+            }
         }
     } else {
         for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
@@ -219,7 +252,7 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
         }
     }
     __syncthreads();
-    lds_fft<T, DIR, NT, RowCfg::E>(buf, pitch, n, a.lg, nl, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, E>(buf, pitch, n, a.lg, nl, reinterpret_cast<const V2<T>*>(a.tw));
 
     // ---- store
     if (STORE == STORE_GRID) {
@@ -271,6 +304,11 @@ struct ColsArgs {
     int outer_nd, outer_Mr;
     int nd;                 // data count along this axis (for pruning)
     const void* tw;
+    // optional: workgroup (0, 0, b) reduces the moment partials of the row pass for field b
+    const double* mom_part;
+    int mom_nblk;
+    double mom_w;           // cell volume
+    double* mom;            // [batch][4]: m0, m1x, m1y, 0
 };
 
 template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E>
@@ -279,6 +317,21 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
     const int n = a.n, C = a.C;
     const int pitch = n + 1;
+    if (a.mom && blockIdx.x == 0 && blockIdx.y == 0) {   // uniform over the workgroup
+        __shared__ double red16[16];
+        const double* part = a.mom_part + (long long)blockIdx.z * a.mom_nblk * 3;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int i = threadIdx.x; i < a.mom_nblk; i += NT)
+            for (int k = 0; k < 3; ++k) s[k] += part[3 * i + k];
+        for (int k = 0; k < 3; ++k) s[k] = wg_sum(s[k], red16);
+        if (threadIdx.x == 0) {
+            double* m = a.mom + 4 * blockIdx.z;
+            m[0] = a.mom_w * s[0];
+            m[1] = a.mom_w * s[1];
+            m[2] = a.mom_w * s[2];
+            m[3] = 0.0;
+        }
+    }
     // XCD-aware order: consecutive hardware workgroup ids go round-robin over the 8 XCDs; give
     // each XCD a contiguous range of column blocks so neighbouring row segments share its L2.
     int cb = blockIdx.x;
@@ -309,6 +362,20 @@ __global__ void k_fill_zero(T* p, long long count) {
     for (; i < count; i += st) p[i] = (T)0;
 }
 
+// 16-byte stores, four per thread and pass (the bulk of a 16-byte aligned buffer)
+__global__ void k_fill_zero16(double2* p, long long count) {
+    const long long st = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double2 z = make_double2(0.0, 0.0);
+    for (; i + 3 * st < count; i += 4 * st) {
+        p[i] = z;
+        p[i + st] = z;
+        p[i + 2 * st] = z;
+        p[i + 3 * st] = z;
+    }
+    for (; i < count; i += st) p[i] = z;
+}
+
 // ---- host launchers ---------------------------------------------------------------------------
 static int ilog2(int v) {
     int l = 0;
@@ -316,9 +383,9 @@ static int ilog2(int v) {
     return l;
 }
 
-template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
-static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
-    constexpr int E = RowCfg::E, NT = RowCfg::NT;
+template <typename T, int DIR, int LOAD, int STORE, typename TIO, int E>
+static int launch_rows_cfg(nlf_plan* p, RowsArgs a, int batch) {
+    constexpr int NT = RowCfg::NT;
     a.lg = ilog2(a.n);
     a.lines_per_wg = std::max(1, E / a.n);
     if (a.n > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
@@ -326,13 +393,24 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     size_t lds = (size_t)a.lines_per_wg * a.n * sizeof(V2<T>);
     static bool attr_set = false;
     if (!attr_set) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE>,
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE>), grid, dim3(NT), lds, p->stream, a);
+    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE, E>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
+}
+
+// LDS element budget of the contiguous-axis kernel for lines of length n: 1024-point lines get
+// one line per workgroup (twice the workgroups of the 2048-element budget)
+static int rows_budget(int n) { return n == 1024 ? 1024 : RowCfg::E; }
+static int rows_lines_per_wg(int n) { return std::max(1, rows_budget(n) / n); }
+
+template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
+static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
+    if (rows_budget(a.n) == 1024) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, 1024>(p, a, batch);
+    return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E>(p, a, batch);
 }
 
 template <typename T, int DIR, bool LP, bool SP, int NT, int E>
@@ -379,11 +457,24 @@ static int type2_forward_t(nlf_plan* p, const void* rho) {
     r.dec2 = p->dec[2];
     r.tw = p->tw_big[d - 1];
     r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
+    // 2D Laplace: the moments m0, m1 of rho (Alg. 1) ride along the row pass
+    const bool mom = (p->kernel == NLF_LAPLACE2D);
+    if (mom) {
+        r.mom_part = p->red;
+        r.L0 = p->L[0]; r.L1 = p->L[1]; r.h0 = p->h[0]; r.h1 = p->h[1];
+    }
     NLF_TRY((launch_rows<T, -1, LOAD_RHO, STORE_GRID>(p, r, p->batch)));
     if (d == 2) {
         ColsArgs c{};
         c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[0]; c.inner = p->Mr[1];
         c.nd = p->n[0]; c.tw = p->tw_big[0];
+        if (mom) {
+            const int lpw = rows_lines_per_wg(p->Mr[1]);   // the row pass's grid
+            c.mom_part = p->red;
+            c.mom_nblk = (p->n[0] + lpw - 1) / lpw;
+            c.mom_w = p->h[0] * p->h[1];
+            c.mom = p->mom;
+        }
         NLF_TRY((launch_cols<T, -1, true, false>(p, c, 1, p->batch)));
     } else {
         ColsArgs c{};
@@ -485,10 +576,15 @@ int fft_full(nlf_plan* p, void* data, int dir, int batch) {
 }
 
 int fill_zero(nlf_plan* p, void* ptr, size_t bytes) {
-    long long words = (long long)(bytes / 8);
-    int blocks = (int)std::min<long long>((words + 255) / 256, 8192);
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_fill_zero<double>), dim3(blocks), dim3(256), 0, p->stream, (double*)ptr, words);
+    // device buffers of the plan are 256-byte aligned; sizes are multiples of 8 bytes
+    const long long n16 = (long long)(bytes / 16);
+    if (n16 > 0) {
+        const int blocks = (int)std::max<long long>(1, std::min<long long>((n16 + 1023) / 1024, 2048));
+        hipLaunchKernelGGL(k_fill_zero16, dim3(blocks), dim3(256), 0, p->stream, (double2*)ptr, n16);
+    }
+    if (bytes % 16)
+        hipLaunchKernelGGL((k_fill_zero<double>), dim3(1), dim3(64), 0, p->stream, (double*)ptr + 2 * n16,
+                           (long long)((bytes % 16) / 8));
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }

@@ -148,7 +148,6 @@ int fill_zero(nlf_plan* p, void* ptr, size_t bytes);
 int set_items(nlf_plan* p, int cap);                          // rebuild the gather work items
 
 // NUFFT stages (nufft.hip)
-int moments(nlf_plan* p, const void* rho);
 int interp(nlf_plan* p, int mode, void* out);                 // mode: 0 potential -> cbuf, 1 type-2 -> out
 int spread(nlf_plan* p);                                      // cbuf -> grid_b
 int fold_c(nlf_plan* p, const void* c);                       // canonical full c -> cbuf (sorted, folded)

@@ -789,50 +789,6 @@ __global__ void k_fold(const V2<T>* __restrict__ c, long long cstride, V2<T>* __
 }
 
 // ---- FP64 moments of the density (2D Laplace subtraction, Alg. 1 first step) -------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_moments_partial(const T* __restrict__ rho, long long N, int n1,
-                                                         double L0, double L1, double h0, double h1,
-                                                         double* __restrict__ part) {
-    const int b = blockIdx.y;
-    const T* r = rho + (long long)b * N;
-    double s0 = 0, sx = 0, sy = 0;
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long long)gridDim.x * 256) {
-        int j0 = (int)(i / n1), j1 = (int)(i - (long long)j0 * n1);
-        double v = (double)r[i];
-        s0 += v;
-        sx += v * (-L0 + j0 * h0);
-        sy += v * (-L1 + j1 * h1);
-    }
-    __shared__ double sh[3][256];
-    sh[0][threadIdx.x] = s0;
-    sh[1][threadIdx.x] = sx;
-    sh[2][threadIdx.x] = sy;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st)
-            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) part[((long long)b * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = sh[threadIdx.x][0];
-}
-
-__global__ void k_moments_final(const double* __restrict__ part, int nblk, double w, double* __restrict__ mom) {
-    const int b = blockIdx.x;
-    __shared__ double sh[3][256];
-    double a[3] = {0, 0, 0};
-    for (int i = threadIdx.x; i < nblk; i += 256)
-        for (int k = 0; k < 3; ++k) a[k] += part[((long long)b * nblk + i) * 3 + k];
-    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = a[k];
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (threadIdx.x < st)
-            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) mom[4 * b + threadIdx.x] = w * sh[threadIdx.x][0];
-    if (threadIdx.x == 3) mom[4 * b + 3] = 0.0;
-}
-
 // ---- host side ---------------------------------------------------------------------------------
 static NodeArgs node_args(const nlf_plan* p) {
     NodeArgs na{};
@@ -899,10 +855,14 @@ static int gather_spread_t(nlf_plan* p) {
     const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
     dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
     const double qq = exp(-2.0 * p->gc.alpha);
-    if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid (3D)
+    if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid
         double2* g64 = reinterpret_cast<double2*>(p->grid_b);
-        hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G, c,
-                           p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+        if (p->dim == 2)
+            hipLaunchKernelGGL((k_mspread<T, double, MSP, 2, KC>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G, c,
+                               p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+        else
+            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G, c,
+                               p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
     } else if (p->dim == 2) {
         hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh, na,
                            p->gitems, p->ngitems, p->gcand, qq);
@@ -998,22 +958,6 @@ int fold_c(nlf_plan* p, const void* c) {
     return NLF_OK;
 }
 
-int moments(nlf_plan* p, const void* rho) {
-    const int nblk = (int)std::min<long long>((p->N + 255) / 256, 1024);
-    dim3 grid(nblk, p->batch);
-    if (p->prec == NLF_F64)
-        hipLaunchKernelGGL((k_moments_partial<double>), grid, dim3(256), 0, p->stream, (const double*)rho, p->N,
-                           p->n[1], p->L[0], p->L[1], p->h[0], p->h[1], p->red);
-    else
-        hipLaunchKernelGGL((k_moments_partial<float>), grid, dim3(256), 0, p->stream, (const float*)rho, p->N,
-                           p->n[1], p->L[0], p->L[1], p->h[0], p->h[1], p->red);
-    NLF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_moments_final, dim3(p->batch), dim3(256), 0, p->stream, p->red, nblk,
-                       p->h[0] * p->h[1], p->mom);
-    NLF_HIP(hipGetLastError());
-    return NLF_OK;
-}
-
 #define NLF_STAGE(p, id, call)               \
     do {                                     \
         int mk_ = stage_begin(p);            \
@@ -1022,8 +966,7 @@ int moments(nlf_plan* p, const void* rho) {
     } while (0)
 
 int potential(nlf_plan* p, const void* rho, void* u) {
-    const bool lap = p->kernel == NLF_LAPLACE2D;
-    if (lap) NLF_STAGE(p, NLF_STAGE_MOMENTS, moments(p, rho));
+    const bool lap = p->kernel == NLF_LAPLACE2D;   // moments m0, m1: computed by the forward FFT
     NLF_STAGE(p, NLF_STAGE_FFT_FWD, fft_type2_forward(p, rho));
     NLF_STAGE(p, NLF_STAGE_INTERP, interp(p, 0, nullptr));
     NLF_STAGE(p, NLF_STAGE_ZERO, fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
@@ -1066,7 +1009,7 @@ int nlf_plan_set_spread(nlf_plan* p, int mode, int block, int item) {
     if (mode != NLF_SPREAD_GATHER && mode != NLF_SPREAD_SCATTER)
         return set_error(NLF_EINVAL, "spread mode must be NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER");
     if (mode == NLF_SPREAD_SCATTER) {
-        // the scatter kernels accumulate in the plan's precision; FP32 3D plans keep an FP64
+        // the scatter kernels accumulate in the plan's precision; FP32 plans keep an FP64
         // spreading grid for the gather kernels (the FP32 bar needs it)
         if (p->t1_prec != p->prec)
             return set_error(NLF_EINVAL, "this plan spreads into an FP64 grid: only NLF_SPREAD_GATHER");

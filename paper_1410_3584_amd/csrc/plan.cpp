@@ -435,12 +435,12 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
 
     // ---- device buffers ------------------------------------------------------------------------
     const size_t es = elem_size(p->prec);
-    // In 3D the type-1 output is divided by the Gaussian's Fourier coefficients, up to ~e^{pi msp/4}
-    // larger at the corners of the box than at its centre; FP32 rounding of the inverse transform is
-    // amplified by that factor.  FP32 3D plans with output-driven spreading therefore keep the
-    // spreading grid and the inverse FFT in FP64 (node values, the type-2 side and the interpolation
-    // stay FP32).
-    p->t1_prec = (p->prec == NLF_F32 && p->dim == 3 && p->use_gather) ? NLF_F64 : p->prec;
+    // The type-1 output is divided by the Gaussian's Fourier coefficients, up to ~e^{pi msp/4} larger
+    // at the corners of the box than at its centre, so FP32 rounding of the inverse transform is
+    // amplified; and the dense centre of the spreading grid receives many FP32 atomic additions.
+    // FP32 plans with output-driven spreading therefore keep the spreading grid and the inverse FFT
+    // in FP64 (node values, the type-2 side and the interpolation stay FP32).
+    p->t1_prec = (p->prec == NLF_F32 && p->use_gather) ? NLF_F64 : p->prec;
     NLF_TRY(dev_alloc(p, &p->grid_a, (size_t)p->batch * p->G * es));
     NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec)));

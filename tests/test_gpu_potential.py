@@ -98,8 +98,8 @@ def test_spread_decompositions_and_autotune(n, L, kernel, prec):
     cd = torch.tensor(c, dtype=plan.cdtype, device="cuda")
     want = op.type1_direct(cd.cpu().numpy().astype(np.complex128), n, L, k)
     cfgs = [(nlf.SPREAD_GATHER, b, i) for b in (64, 128) for i in (256, 512, 1024, 2048)]
-    if len(n) == 3 and prec == nlf.F32:
-        # FP32 3D plans spread into an FP64 grid, which only the gather kernels fill
+    if prec == nlf.F32:
+        # FP32 plans spread into an FP64 grid, which only the gather kernels fill
         with pytest.raises(nlf.NlfError):
             plan.set_spread(nlf.SPREAD_SCATTER)
     else:
