@@ -148,7 +148,8 @@ int fill_zero(nlf_plan* p, void* ptr, size_t bytes);
 int set_items(nlf_plan* p, int cap);                          // rebuild the gather work items
 
 // NUFFT stages (nufft.hip)
-int interp(nlf_plan* p, int mode, void* out);                 // mode: 0 potential -> cbuf, 1 type-2 -> out
+// mode: 0 potential -> cbuf, 2 type-2 -> out; zero_b: the 2D kernel also clears grid_b
+int interp(nlf_plan* p, int mode, void* out, bool zero_b);
 int spread(nlf_plan* p);                                      // cbuf -> grid_b
 int fold_c(nlf_plan* p, const void* c);                       // canonical full c -> cbuf (sorted, folded)
 int potential(nlf_plan* p, const void* rho, void* u);

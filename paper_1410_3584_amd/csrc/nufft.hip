@@ -531,7 +531,8 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
 // FP64 epilogue (symbol times weight) directly: no atomics, no cross-wave reduction.
 template <typename T, int MSP>
 __global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
-                                                 NodeArgs na, EpiArgs ea, double qq4) {
+                                                 NodeArgs na, EpiArgs ea, double qq4,
+                                                 double2* __restrict__ zero, long long zero16) {
     constexpr int WX = 8 + 2 * MSP - 1, RBX = (WX + 7) / 8;
     constexpr int WY = 16 + 2 * MSP - 1, KS = (WY + 3) / 4;
     // window planes (real, imaginary), column-major: Gp[p * PL + c * PX + r]; PX = 8 mod 32 and
@@ -544,6 +545,15 @@ __global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ g
     __shared__ double Gp[2 * PL];
     __shared__ double nd[kChunk][2];        // fractional parts delta_0, delta_1
     __shared__ int noff[kChunk][2];         // stencil start within the window
+    // the spreading grid that follows is cleared here, a slice per workgroup, in the bandwidth this
+    // compute-bound kernel leaves idle (16-byte stores)
+    if (zero) {
+        const long long nwg = (long long)gridDim.x * gridDim.y;
+        const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const long long per = (zero16 + nwg - 1) / nwg;
+        const long long e = min(zero16, (wg + 1) * per);
+        for (long long i = wg * per + threadIdx.x; i < e; i += 256) zero[i] = make_double2(0.0, 0.0);
+    }
     const int cid = chunk_id(na.nchunks);
     if (cid >= na.nchunks) return;
     const Chunk ch = na.chunks[cid];
@@ -813,13 +823,15 @@ static size_t window_bytes(const nlf_plan* p) {
 static int grid_chunks(const nlf_plan* p) { return ((p->nchunks + 7) / 8) * 8; }
 
 template <typename T, int MSP>
-static int interp_t(nlf_plan* p, const EpiArgs& ea) {
+static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
     NodeArgs na = node_args(p);
     if (p->dim == 2) {
         dim3 grid(grid_chunks(p), p->batch);
         const double qq4 = exp(-32.0 * p->gc.alpha);
+        const size_t bbytes = (size_t)p->batch * p->G * elem_size(p->t1_prec);   // a multiple of 16
         hipLaunchKernelGGL((k_binterp2<T, MSP>), grid, dim3(256), 0, p->stream,
-                           reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4);
+                           reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4,
+                           zero_b ? (double2*)p->grid_b : nullptr, (long long)(bbytes / 16));
         NLF_HIP(hipGetLastError());
         return NLF_OK;
     }
@@ -924,14 +936,14 @@ static EpiArgs epi_args(const nlf_plan* p, int mode, void* out, long long ostrid
     return ea;
 }
 
-int interp(nlf_plan* p, int mode, void* out) {
+int interp(nlf_plan* p, int mode, void* out, bool zero_b) {
     EpiArgs ea;
     if (mode == MODE_TYPE2) ea = epi_args(p, MODE_TYPE2, out, p->M);
     else ea = epi_args(p, p->kernel == NLF_LAPLACE2D ? MODE_LAPLACE : MODE_COULOMB, p->cbuf, p->Mh);
     if (p->prec == NLF_F64) {
-        switch (p->msp) { NLF_MSP_CASES_F64(interp_t, double, p, ea) default: return bad_msp(p); }
+        switch (p->msp) { NLF_MSP_CASES_F64(interp_t, double, p, ea, zero_b) default: return bad_msp(p); }
     }
-    switch (p->msp) { NLF_MSP_CASES_F32(interp_t, float, p, ea) default: return bad_msp(p); }
+    switch (p->msp) { NLF_MSP_CASES_F32(interp_t, float, p, ea, zero_b) default: return bad_msp(p); }
 }
 
 static int spread_only(nlf_plan* p) {
@@ -968,8 +980,11 @@ int fold_c(nlf_plan* p, const void* c) {
 int potential(nlf_plan* p, const void* rho, void* u) {
     const bool lap = p->kernel == NLF_LAPLACE2D;   // moments m0, m1: computed by the forward FFT
     NLF_STAGE(p, NLF_STAGE_FFT_FWD, fft_type2_forward(p, rho));
-    NLF_STAGE(p, NLF_STAGE_INTERP, interp(p, 0, nullptr));
-    NLF_STAGE(p, NLF_STAGE_ZERO, fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
+    // 2D: the interpolation kernel also clears the spreading grid (the zero stage then reports 0)
+    const bool fused_zero = (p->dim == 2);
+    NLF_STAGE(p, NLF_STAGE_INTERP, interp(p, 0, nullptr, fused_zero));
+    if (!fused_zero)
+        NLF_STAGE(p, NLF_STAGE_ZERO, fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_STAGE(p, NLF_STAGE_SPREAD, spread_only(p));
     NLF_STAGE(p, NLF_STAGE_FFT_INV, fft_type1_inverse(p, u, lap));
     return NLF_OK;
@@ -992,7 +1007,7 @@ int nlf_type2(nlf_plan* p, const void* rho, void* rhohat) {
     clear_error();
     if (!p || !rho || !rhohat) return set_error(NLF_EINVAL, "plan, rho and rhohat must not be NULL");
     NLF_TRY(fft_type2_forward(p, rho));
-    return interp(p, MODE_TYPE2, rhohat);
+    return interp(p, MODE_TYPE2, rhohat, false);
 }
 
 int nlf_type1(nlf_plan* p, const void* c, void* u) {
