@@ -242,6 +242,31 @@ def test_largest_grid_1024_sampled():
     assert np.max(np.abs(np.array([u[p] for p in pts]) - want)) <= 1e-10 * np.max(np.abs(u))
 
 
+def test_dynamics_workload_256_sampled():
+    """3D dynamics workload at full size: 256^3 on [-12,12]^3, Coulomb kernel, 256x256x512 nodes,
+    rho = |psi0|^2 of the seeded phase-modulated Gaussian.  Type-2 at sampled nodes and the
+    potential at sampled grid points (from the GPU's node values over the full node set) against
+    the oracle's direct sums, <= 1e-10."""
+    print("[256^3 sampled]", flush=True)
+    n, L = (256, 256, 256), (12.0, 12.0, 12.0)
+    psi0 = inputs.psi0_phase_modulated(n, L, seed=0)
+    rho = np.abs(psi0) ** 2
+    plan = nlf.Plan(n, L, nlf.COULOMB3D)
+    k, w = plan.nodes()
+    rd = to_dev(rho, 0)
+    rh = plan.type2(rd).cpu().numpy()
+    rng = np.random.default_rng(3)
+    sel = rng.choice(len(k), 16, replace=False)
+    scale = np.max(np.abs(rh))
+    assert np.max(np.abs(rh[sel] - op.type2_direct(rho, n, L, k[sel]))) <= 1e-10 * scale
+    c = op.symbol_coeffs(nlf.COULOMB3D, k, w, np.linalg.norm(k, axis=1), rh)
+    del rh
+    u = plan.potential(rd).cpu().numpy()
+    pts = [tuple(rng.integers(0, 256, size=3)) for _ in range(6)] + [(128, 128, 128), (0, 255, 7)]
+    want = oracle_u_at(pts, c, k, n, L, nlf.COULOMB3D)
+    assert np.max(np.abs(np.array([u[p] for p in pts]) - want)) <= 1e-10 * np.max(np.abs(u))
+
+
 def test_coulomb3d_workload_closed_form():
     """3D check workload: rho = e^{-|x|^2} on 32^3 of [-8,8]^3, 32x32x64 nodes; continuum error
     is the ball/angular floor (< 5e-5, see the oracle pins), parity <= 1e-10."""

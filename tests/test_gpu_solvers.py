@@ -195,6 +195,39 @@ def test_gs_batch_over_plans_of_uneven_size(graph):
             assert abs(stats[i][j]["E"] - st[0]["E"]) < 1e-10
 
 
+def test_gs_batched_workload_full():
+    """Batched 2D ground-state workload at full size: 64 instances on [-16,16]^2 with grids drawn
+    from {64^2, 128^2, 256^2}, beta ~ U[10,1000], gamma ~ U[0.5,2], Coulomb kernel, FP32 bulk and
+    FP64 polish, autotuned spreading, solved concurrently (one plan and stream per size).  Every
+    field reaches the 1e-10 residual; sampled fields equal their own FP64 solve."""
+    print("[gs batched workload]", flush=True)
+    inst = inputs.ground_state_batch_2d(seed=3, count=64)
+    groups = {}
+    for d in inst:
+        groups.setdefault(d["n"][0], []).append(d)
+    keys = sorted(groups)
+    streams = [torch.cuda.Stream() for _ in keys]
+    plans = [nlf.Plan((k, k), (16.0, 16.0), nlf.COULOMB2D, prec=nlf.F32, batch=len(groups[k]),
+                      stream=s.cuda_stream) for k, s in zip(keys, streams)]
+    for p in plans:
+        p.autotune(reps=2)
+    betas = [[d["beta"] for d in groups[k]] for k in keys]
+    gams = [[d["gamma"] for d in groups[k]] for k in keys]
+    outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.25, eps0=1e-10, max_iter=5000,
+                                                 mixed=True)
+    assert status == nlf.OK
+    assert sum(len(a) for a in stats) == 64
+    assert max(s["residual"] for a in stats for s in a) <= 1e-10
+    rng = np.random.default_rng(0)
+    for i, k in enumerate(keys):
+        j = int(rng.integers(0, len(groups[k])))
+        single = nlf.Plan((k, k), (16.0, 16.0), nlf.COULOMB2D)
+        psi, st, s1 = single.ground_state(betas[i][j], gams[i][j], tau=0.25, eps0=1e-10, max_iter=5000)
+        assert s1 == nlf.OK
+        assert abs(stats[i][j]["E"] - st[0]["E"]) <= 1e-9 * abs(st[0]["E"]), (k, j)
+        assert rel_err(outs[i][j].cpu().numpy().astype(np.float64), psi.cpu().numpy()) < 1e-6
+
+
 # ---- dynamics ---------------------------------------------------------------------------------
 
 def _psi0(n, L, seed=0):
