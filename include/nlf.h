@@ -95,6 +95,7 @@ typedef struct {
     int spread_block;      /* candidates per block of the gather kernel (64 or 128)         */
     int spread_item;       /* candidates per work item of the gather kernel (256 .. 2048)   */
     int gather_available;  /* 1 if the plan built its gather-tile candidate lists           */
+    int bins_available;    /* 1 if the neighbour-bin gather applies (grids large enough)    */
 } nlf_plan_info;
 
 /* Create a plan for the potential of `kernel` on `box` (Sec. 2.1 nodes and weights, Eq.
@@ -112,6 +113,10 @@ int nlf_plan_get_info(const nlf_plan* plan, nlf_plan_info* info);
  *   `block` at a time, one atomic per cell and item.
  * NLF_SPREAD_SCATTER: each node adds its stencil into an LDS window of its bin (LDS atomics),
  *   then the window into the grid.
+ * NLF_SPREAD_BINS: as GATHER, but a tile reads its candidates as the node ranges of a fixed box
+ *   of neighbouring node bins (bins have the tile's shape) instead of a stored per-tile list:
+ *   about 1.4x (3D) to 1.6x (2D) more candidates, no list memory; the default where the lists
+ *   would be too large (e.g. 256^3).  Items of 512, 1024 or 2048 candidates.
  * nlf_plan_set_spread selects one (block 64 or 128; item 256, 512, 1024 or 2048; GATHER needs
  * the plan's candidate lists, info.gather_available; SCATTER is not available to FP32 plans with
  * candidate lists, which spread into an FP64 grid); returns NLF_EINVAL otherwise.
@@ -119,7 +124,7 @@ int nlf_plan_get_info(const nlf_plan* plan, nlf_plan_info* info);
  * set to 1, `reps` timed calls each, default 5 if reps <= 0), keeps the fastest and returns
  * its time per call in *best_ms (may be NULL).  Results are the same up to the summation order
  * of floating-point atomics.  Synchronises the plan's stream.                               */
-enum { NLF_SPREAD_GATHER = 0, NLF_SPREAD_SCATTER = 1 };
+enum { NLF_SPREAD_GATHER = 0, NLF_SPREAD_SCATTER = 1, NLF_SPREAD_BINS = 2 };
 int nlf_plan_set_spread(nlf_plan* plan, int mode, int block, int item);
 int nlf_plan_autotune(nlf_plan* plan, int reps, double* best_ms);
 

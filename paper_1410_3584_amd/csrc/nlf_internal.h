@@ -52,6 +52,8 @@ struct GItem {
 };
 constexpr int kMChunk = 128;
 constexpr int kMItem = 1024;
+// neighbour-bin gather: most neighbour bins a tile may read (5 x 9 x 9 at msp 16 in 3D)
+constexpr int kMaxNbrBins = 512;
 
 // Gaussian-gridding constants handed to the kernels by value.
 struct GaussConst {
@@ -101,9 +103,15 @@ struct nlf_plan {
     int spread_mode = 0;        // NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER
     int spread_kc = 64;         // candidates per block of the gather kernel
     int item_cap = nlf::kMItem; // candidates per work item
-    std::vector<long long> gtile_off;   // per gather tile: first candidate (ntiles + 1 entries)
+    std::vector<long long> gtile_off;   // explicit lists: per gather tile, first candidate
     int gng[3] = {1, 1, 1};     // gather tiles per axis
     long long gitems_cap = 0;   // GItem slots allocated on the device
+    int items_bins = 0;         // the uploaded items index neighbour-bin streams
+    // neighbour-bin gather (node bins = gather tiles)
+    int gather_impl_ok = 0;
+    int* bin_off = nullptr;     // [nbins + 1] first sorted node of each bin
+    int impl_lo[3] = {0, 0, 0}, impl_n[3] = {1, 1, 1};   // neighbour bins per axis: t + lo .. t + lo + n - 1
+    std::vector<long long> vtile_off;   // per tile: first candidate of its neighbour-bin stream
     double* dec[3] = {nullptr, nullptr, nullptr};   // 1 / c_g(j - n/2), length n_i
     void* tw_big[3] = {nullptr, nullptr, nullptr};  // twiddles of length Mr_i (plan precision)
     void* tw_small[3] = {nullptr, nullptr, nullptr};// twiddles of length n_i (solver FFTs)
@@ -145,7 +153,7 @@ int fft_type2_forward(nlf_plan* p, const void* rho);          // rho -> grid_a (
 int fft_type1_inverse(nlf_plan* p, void* u, bool add_u1);     // grid_b -> u (pruned, fused postcorrect)
 int fft_full(nlf_plan* p, void* data, int dir, int batch);    // n-grid complex FFT in place, all axes
 int fill_zero(nlf_plan* p, void* ptr, size_t bytes);
-int set_items(nlf_plan* p, int cap);                          // rebuild the gather work items
+int set_items(nlf_plan* p, int cap, bool bins);               // rebuild the gather work items
 
 // NUFFT stages (nufft.hip)
 // mode: 0 potential -> cbuf, 2 type-2 -> out; zero_b: the 2D kernel also clears grid_b

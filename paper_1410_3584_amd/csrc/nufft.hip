@@ -395,11 +395,67 @@ __device__ __forceinline__ int mrow_slot(int k, int chunk) {
     return ((chunk ^ ((k >> 1) & 7) ^ ((k & 1) << 2)) & 7);
 }
 
-template <typename T, typename TG, int MSP, int DIM, int KC>
+// Neighbour-bin candidate streams: the node bins have the tile's shape; tile t reads the bins
+// t + lo_i .. t + lo_i + n_i - 1 (periodic) in lexicographic order, each bin a contiguous range
+// of sorted nodes.
+struct BinArgs {
+    const int* bin_off;     // [nbins + 1] first sorted node of each bin
+    int lo[3], n[3], NB[3];
+};
+
+// The table of tile (g0, g1, g2)'s neighbour bins in LDS: pref[i] = candidates before bin i of the
+// stream (pref[nbn] = total), start[i] = its first node.  Every thread of the workgroup calls it.
+template <int NT>
+__device__ __forceinline__ int bin_table(const BinArgs& ba, int g0, int g1, int g2, int* pref, int* tmp,
+                                         int* start) {
+    const int nbn = ba.n[0] * ba.n[1] * ba.n[2];
+    const int t = threadIdx.x;
+    for (int i = t; i < nbn; i += NT) {
+        const int ia = i / (ba.n[1] * ba.n[2]), ib = (i / ba.n[2]) % ba.n[1], ic = i % ba.n[2];
+        const int b0 = (g0 + ba.lo[0] + ia + ba.NB[0]) % ba.NB[0];
+        const int b1 = (g1 + ba.lo[1] + ib + ba.NB[1]) % ba.NB[1];
+        const int b2 = (g2 + ba.lo[2] + ic + ba.NB[2]) % ba.NB[2];
+        const long long bid = ((long long)b0 * ba.NB[1] + b1) * ba.NB[2] + b2;
+        const int s0 = ba.bin_off[bid];
+        start[i] = s0;
+        pref[i + 1] = ba.bin_off[bid + 1] - s0;
+    }
+    if (t == 0) pref[0] = 0;
+    __syncthreads();
+    // inclusive scan of pref[1..nbn] (Hillis-Steele, ping-pong through tmp)
+    int* a = pref;
+    int* c = tmp;
+    for (int d = 1; d < nbn; d <<= 1) {
+        for (int i = 1 + t; i <= nbn; i += NT) c[i] = a[i] + ((i - d >= 1) ? a[i - d] : 0);
+        if (t == 0) c[0] = 0;
+        __syncthreads();
+        int* x = a;
+        a = c;
+        c = x;
+    }
+    if (a != pref) {
+        for (int i = t; i <= nbn; i += NT) pref[i] = a[i];
+        __syncthreads();
+    }
+    return nbn;
+}
+
+// sorted node at position pos (0 <= pos < pref[nbn]) of a neighbour-bin stream
+__device__ __forceinline__ int bin_node(const int* pref, const int* start, int nbn, int pos) {
+    int lo = 0, hi = nbn;   // pref[lo] <= pos < pref[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= pos) lo = mid;
+        else hi = mid;
+    }
+    return start[lo] + (pos - pref[lo]);
+}
+
+template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS>
 __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
-                                                        const int* __restrict__ cand, double qq) {
+                                                        const int* __restrict__ cand, double qq, BinArgs ba) {
     constexpr int NW = 2 * KC / 64;   // waves; each multiplies KC / NW candidates of a block
     static_assert(KC % (4 * NW) == 0 && (KC / NW) % 8 == 0, "whole pairs of MFMA steps per wave");
     static_assert(2 * KC * 16 >= NW * 4 * 64, "wave partials fit S");
@@ -419,13 +475,19 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
     const int kb = wv * (KC / NW);
     // four accumulators: independent product chains keep the FP64 matrix pipe busy
     d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    // neighbour-bin streams: the tile's bin table (pref, start) in LDS
+    __shared__ int nb_pref[BINS ? kMaxNbrBins + 1 : 1], nb_tmp[BINS ? kMaxNbrBins + 1 : 1];
+    __shared__ int nb_start[BINS ? kMaxNbrBins : 1];
+    int nbn = 0;
+    if (BINS) nbn = bin_table<2 * KC>(ba, it.g0, it.g1, it.g2, nb_pref, nb_tmp, nb_start);
     // node data of this thread's candidate in the current block, loaded one block ahead so that
     // the loads overlap the previous block's matrix products
     double sa = 0.0, sb = 0.0;
     V2<T> cv = mk2<T>((T)0, (T)0);
     auto fetch = [&](int base) {
         if (base + k < it.count) {
-            const int node = cand[it.start + base + k];
+            const int node = BINS ? bin_node(nb_pref, nb_start, nbn, (int)it.start + base + k)
+                                  : cand[it.start + base + k];
             if (is_a) {
                 sa = na.s[0][node];
                 cv = cbuf[(long long)b * cstride + node];
@@ -835,7 +897,9 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
         NLF_HIP(hipGetLastError());
         return NLF_OK;
     }
-    if (p->use_gather) {
+    // (the tile-gathered 3D interpolation reads the explicit candidate lists through the work
+    // items; with neighbour-bin items in use it takes the plane-streamed kernel)
+    if (p->use_gather && !p->items_bins) {
         NLF_TRY(fill_zero(p, p->iacc, (size_t)p->batch * p->Mh * 2 * sizeof(double)));
         dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
         const double qq = exp(-2.0 * p->gc.alpha);
@@ -860,27 +924,34 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
     return NLF_OK;
 }
 
-template <typename T, int MSP, int KC>
+template <typename T, int MSP, int KC, bool BINS>
 static int gather_spread_t(nlf_plan* p) {
     NodeArgs na = node_args(p);
     V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
     const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
     dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
     const double qq = exp(-2.0 * p->gc.alpha);
+    BinArgs ba{};
+    ba.bin_off = p->bin_off;
+    for (int i = 0; i < 3; ++i) {
+        ba.lo[i] = p->impl_lo[i];
+        ba.n[i] = p->impl_n[i];
+        ba.NB[i] = p->gng[i];
+    }
     if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid
         double2* g64 = reinterpret_cast<double2*>(p->grid_b);
         if (p->dim == 2)
-            hipLaunchKernelGGL((k_mspread<T, double, MSP, 2, KC>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G, c,
-                               p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+            hipLaunchKernelGGL((k_mspread<T, double, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
+                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba);
         else
-            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G, c,
-                               p->Mh, na, p->gitems, p->ngitems, p->gcand, qq);
+            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
+                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba);
     } else if (p->dim == 2) {
-        hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh, na,
-                           p->gitems, p->ngitems, p->gcand, qq);
+        hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
+                           na, p->gitems, p->ngitems, p->gcand, qq, ba);
     } else {
-        hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, KC>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh, na,
-                           p->gitems, p->ngitems, p->gcand, qq);
+        hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
+                           na, p->gitems, p->ngitems, p->gcand, qq, ba);
     }
     NLF_HIP(hipGetLastError());
     return NLF_OK;
@@ -889,7 +960,9 @@ static int gather_spread_t(nlf_plan* p) {
 template <typename T, int MSP>
 static int spread_t(nlf_plan* p) {
     if (p->use_gather && p->spread_mode == NLF_SPREAD_GATHER)
-        return p->spread_kc == 128 ? gather_spread_t<T, MSP, 128>(p) : gather_spread_t<T, MSP, 64>(p);
+        return p->spread_kc == 128 ? gather_spread_t<T, MSP, 128, false>(p) : gather_spread_t<T, MSP, 64, false>(p);
+    if (p->gather_impl_ok && p->spread_mode == NLF_SPREAD_BINS)
+        return p->spread_kc == 128 ? gather_spread_t<T, MSP, 128, true>(p) : gather_spread_t<T, MSP, 64, true>(p);
     NodeArgs na = node_args(p);
     V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
     const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
@@ -1021,21 +1094,23 @@ int nlf_type1(nlf_plan* p, const void* c, void* u) {
 int nlf_plan_set_spread(nlf_plan* p, int mode, int block, int item) {
     clear_error();
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
-    if (mode != NLF_SPREAD_GATHER && mode != NLF_SPREAD_SCATTER)
-        return set_error(NLF_EINVAL, "spread mode must be NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER");
+    if (mode != NLF_SPREAD_GATHER && mode != NLF_SPREAD_SCATTER && mode != NLF_SPREAD_BINS)
+        return set_error(NLF_EINVAL, "spread mode must be NLF_SPREAD_GATHER, _SCATTER or _BINS");
     if (mode == NLF_SPREAD_SCATTER) {
         // the scatter kernels accumulate in the plan's precision; FP32 plans keep an FP64
         // spreading grid for the gather kernels (the FP32 bar needs it)
         if (p->t1_prec != p->prec)
-            return set_error(NLF_EINVAL, "this plan spreads into an FP64 grid: only NLF_SPREAD_GATHER");
+            return set_error(NLF_EINVAL, "this plan spreads into an FP64 grid: only the gather modes");
         p->spread_mode = mode;
         return NLF_OK;
     }
-    if (!p->use_gather) return set_error(NLF_EINVAL, "this plan has no gather-tile candidate lists");
+    const bool bins = (mode == NLF_SPREAD_BINS);
+    if (!bins && !p->use_gather) return set_error(NLF_EINVAL, "this plan has no gather-tile candidate lists");
+    if (bins && !p->gather_impl_ok) return set_error(NLF_EINVAL, "the neighbour-bin gather does not apply to this plan");
     if (block != 64 && block != 128) return set_error(NLF_EINVAL, "block must be 64 or 128");
-    if (item != 256 && item != 512 && item != 1024 && item != 2048)
-        return set_error(NLF_EINVAL, "item must be 256, 512, 1024 or 2048");
-    if (item != p->item_cap) NLF_TRY(set_items(p, item));
+    if (!(item == 512 || item == 1024 || item == 2048 || (item == 256 && !bins)))
+        return set_error(NLF_EINVAL, "item must be 256 (lists only), 512, 1024 or 2048");
+    if (item != p->item_cap || (p->items_bins != 0) != bins) NLF_TRY(set_items(p, item, bins));
     p->spread_mode = mode;
     p->spread_kc = block;
     return NLF_OK;
@@ -1050,6 +1125,9 @@ int nlf_plan_autotune(nlf_plan* p, int reps, double* best_ms) {
     if (p->use_gather)
         for (int block : {64, 128})
             for (int item : {256, 512, 1024, 2048}) cfgs.push_back({NLF_SPREAD_GATHER, block, item});
+    if (p->gather_impl_ok)
+        for (int block : {64, 128})
+            for (int item : {512, 1024, 2048}) cfgs.push_back({NLF_SPREAD_BINS, block, item});
     if (p->t1_prec == p->prec) cfgs.push_back({NLF_SPREAD_SCATTER, p->spread_kc, p->item_cap});
     if (cfgs.empty()) return set_error(NLF_EINVAL, "no spreading decomposition to time");
     // node values 1: every tile the candidates reach receives a nonzero sum

@@ -25,11 +25,12 @@ void clear_error() { g_err[0] = 0; }
 size_t elem_size(int prec) { return prec == NLF_F64 ? 16 : 8; }
 
 // Work items of the gather kernels: the candidates of each tile cut into pieces of <= cap.
-int set_items(nlf_plan* p, int cap) {
+int set_items(nlf_plan* p, int cap, bool bins) {
     std::vector<GItem> items;
     const long long ntiles = (long long)p->gng[0] * p->gng[1] * p->gng[2];
+    const std::vector<long long>& off = bins ? p->vtile_off : p->gtile_off;
     for (long long t = 0; t < ntiles; ++t) {
-        const long long beg = p->gtile_off[t], end = p->gtile_off[t + 1];
+        const long long beg = off[t], end = off[t + 1];
         const int g2 = (int)(t % p->gng[2]);
         const int g1 = (int)((t / p->gng[2]) % p->gng[1]);
         const int g0 = (int)(t / ((long long)p->gng[2] * p->gng[1]));
@@ -39,7 +40,7 @@ int set_items(nlf_plan* p, int cap) {
             it.g1 = g1;
             it.g2 = g2;
             it.count = (int)std::min<long long>(cap, end - s0);
-            it.start = s0;
+            it.start = bins ? s0 - beg : s0;   // bins: offset within the tile's candidate stream
             items.push_back(it);
         }
     }
@@ -49,6 +50,7 @@ int set_items(nlf_plan* p, int cap) {
     if (!items.empty()) NLF_HIP(hipMemcpy(p->gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice));
     p->ngitems = (int)items.size();
     p->item_cap = cap;
+    p->items_bins = bins ? 1 : 0;
     return NLF_OK;
 }
 
@@ -216,10 +218,11 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         p->post /= p->Mr[i];
     }
 
-    // tiles
-    // (2D bins of 8 x 16 cells: the matrix-core interpolation stages one bin's window per workgroup)
+    // tiles: node bins of the gather-tile shape, 8 x 16 cells (2D) or 8 x 4 x 4 (3D): the 2D
+    // interpolation stages one bin's window per workgroup, and the neighbour-bin gather reads a
+    // tile's candidates as whole bins
     for (int i = 0; i < 3; ++i) {
-        int t = (p->dim == 2) ? (i == 0 ? 8 : 16) : 8;
+        int t = (p->dim == 2) ? (i == 0 ? 8 : 16) : (i == 0 ? 8 : 4);
         if (i >= p->dim) t = 1;
         p->tile[i] = std::min(t, p->Mr[i]);
         p->window[i] = (i < p->dim) ? p->tile[i] + 2 * p->msp - 1 : 1;
@@ -391,18 +394,81 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
                             cand[pos[tid]++] = (int)j;
                         }
             }
-            p->gtile_off.assign(tcount.begin(), tcount.end());
-            for (int i = 0; i < 3; ++i) p->gng[i] = ng[i];
+            p->gtile_off.assign(tcount.begin(), tcount.end());   // explicit lists
             p->use_gather = 1;
             NLF_TRY(upload(p, (void**)&p->gcand, cand.data(), std::max<size_t>(1, cand.size()) * sizeof(int)));
-            // room for the finest item size the decomposition allows (256 candidates)
-            long long most = 0;
-            for (long long t = 0; t < ntiles; ++t) most += (tcount[t + 1] - tcount[t] + 255) / 256;
-            p->gitems_cap = std::max(1LL, most);
+        }
+        for (int i = 0; i < 3; ++i) p->gng[i] = ng[i];
+
+        // Neighbour-bin gather: with node bins of the tile's shape, the nodes whose stencil can
+        // reach tile t lie in the bins t + lo_i .. t + lo_i + nn_i - 1 per axis,
+        // lo = floor(-msp / T), hi = floor((T + msp - 2) / T).  A tile's candidates are those bins'
+        // node ranges, read in place (no per-pair list).  Needs more bins per axis than nn_i (no
+        // bin counted twice) and Mr_i >= 2 msp + T_i (single-representative tile weights).
+        bool impl = true;
+        for (int i = 0; i < 3; ++i) {
+            if (i >= p->dim) {
+                p->impl_lo[i] = 0;
+                p->impl_n[i] = 1;
+                continue;
+            }
+            const int T = gt[i];
+            const int lo = -((p->msp + T - 1) / T);        // floor(-msp / T)
+            const int hi = (T + p->msp - 2) / T;
+            p->impl_lo[i] = lo;
+            p->impl_n[i] = hi - lo + 1;
+            impl = impl && p->tile[i] == T && nb[i] >= p->impl_n[i] && p->Mr[i] >= 2 * p->msp + T;
+        }
+        if (impl && p->impl_n[0] * p->impl_n[1] * p->impl_n[2] <= kMaxNbrBins) {
+            NLF_TRY(upload(p, (void**)&p->bin_off, cnt.data(), cnt.size() * sizeof(int)));
+            p->vtile_off.assign(ntiles + 1, 0);
+            for (long long t = 0; t < ntiles; ++t) {
+                const int t2 = (int)(t % ng[2]), t1 = (int)((t / ng[2]) % ng[1]);
+                const int t0 = (int)(t / ((long long)ng[2] * ng[1]));
+                long long tot = 0;
+                for (int a = 0; a < p->impl_n[0]; ++a) {
+                    const int b0 = ((t0 + p->impl_lo[0] + a) % nb[0] + nb[0]) % nb[0];
+                    for (int b = 0; b < p->impl_n[1]; ++b) {
+                        const int b1 = ((t1 + p->impl_lo[1] + b) % nb[1] + nb[1]) % nb[1];
+                        for (int c = 0; c < p->impl_n[2]; ++c) {
+                            const int b2 = ((t2 + p->impl_lo[2] + c) % nb[2] + nb[2]) % nb[2];
+                            const long long bid = ((long long)b0 * nb[1] + b1) * nb[2] + b2;
+                            tot += cnt[bid + 1] - cnt[bid];
+                        }
+                    }
+                }
+                p->vtile_off[t + 1] = p->vtile_off[t] + tot;
+            }
+            p->gather_impl_ok = 1;
+        }
+        // one work-item buffer for every decomposition: room for the finest item sizes allowed
+        // (256 candidates from the explicit lists, 512 from the neighbour bins)
+        long long most = 1;
+        if (p->use_gather) {
+            long long m = 0;
+            for (long long t = 0; t < ntiles; ++t) m += (p->gtile_off[t + 1] - p->gtile_off[t] + 255) / 256;
+            most = std::max(most, m);
+        }
+        if (p->gather_impl_ok) {
+            long long m = 0;
+            for (long long t = 0; t < ntiles; ++t) m += (p->vtile_off[t + 1] - p->vtile_off[t] + 511) / 512;
+            most = std::max(most, m);
+        }
+        if (p->use_gather || p->gather_impl_ok) {
+            p->gitems_cap = most;
             NLF_TRY(dev_alloc(p, (void**)&p->gitems, (size_t)p->gitems_cap * sizeof(GItem)));
-            // default work items: 512 candidates for the wide FP64 stencils, 256 for narrower ones
-            // (the fastest on the 2D workloads measured; nlf_plan_autotune picks per plan)
-            NLF_TRY(set_items(p, p->msp >= 10 ? 512 : 256));
+        }
+        // default: the explicit lists with 512-candidate items for the wide FP64 stencils and 256
+        // for narrower ones (the fastest on the 2D workloads measured; nlf_plan_autotune picks
+        // per plan); neighbour bins with 1024-candidate items where the lists were not built
+        if (p->use_gather) {
+            p->spread_mode = NLF_SPREAD_GATHER;
+            NLF_TRY(set_items(p, p->msp >= 10 ? 512 : 256, false));
+        } else if (p->gather_impl_ok) {
+            p->spread_mode = NLF_SPREAD_BINS;
+            NLF_TRY(set_items(p, 1024, true));
+        } else {
+            p->spread_mode = NLF_SPREAD_SCATTER;
         }
     }
 
@@ -440,7 +506,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     // amplified; and the dense centre of the spreading grid receives many FP32 atomic additions.
     // FP32 plans with output-driven spreading therefore keep the spreading grid and the inverse FFT
     // in FP64 (node values, the type-2 side and the interpolation stay FP32).
-    p->t1_prec = (p->prec == NLF_F32 && p->use_gather) ? NLF_F64 : p->prec;
+    p->t1_prec = (p->prec == NLF_F32 && (p->use_gather || p->gather_impl_ok)) ? NLF_F64 : p->prec;
     NLF_TRY(dev_alloc(p, &p->grid_a, (size_t)p->batch * p->G * es));
     NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
     NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
@@ -622,10 +688,11 @@ int nlf_plan_get_info(const nlf_plan* p, nlf_plan_info* info) {
     info->n_nodes = p->M;
     info->n_half = p->Mh;
     info->workspace_bytes = p->workspace_bytes;
-    info->spread_mode = (p->use_gather && p->spread_mode == NLF_SPREAD_GATHER) ? NLF_SPREAD_GATHER : NLF_SPREAD_SCATTER;
+    info->spread_mode = p->spread_mode;
     info->spread_block = p->spread_kc;
     info->spread_item = p->item_cap;
     info->gather_available = p->use_gather;
+    info->bins_available = p->gather_impl_ok;
     return NLF_OK;
 }
 

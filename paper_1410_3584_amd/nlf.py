@@ -24,7 +24,7 @@ EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan
            "nlf_ws_set_standardisation", "nlf_ws_forward", "nlf_ws_loss_grad", "nlf_ws_train",
            "nlf_ws_predict", "nlf_ws_ground_state", "nlf_plan_set_spread", "nlf_plan_autotune"]
 STAGES = ["moments", "fft_fwd", "interp", "zero", "spread", "fft_inv"]
-SPREAD_GATHER, SPREAD_SCATTER = 0, 1
+SPREAD_GATHER, SPREAD_SCATTER, SPREAD_BINS = 0, 1, 2
 
 
 class Box(ctypes.Structure):
@@ -45,7 +45,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_nodes", ctypes.c_longlong), ("n_half", ctypes.c_longlong),
                 ("workspace_bytes", ctypes.c_longlong), ("spread_mode", ctypes.c_int),
                 ("spread_block", ctypes.c_int), ("spread_item", ctypes.c_int),
-                ("gather_available", ctypes.c_int)]
+                ("gather_available", ctypes.c_int), ("bins_available", ctypes.c_int)]
 
 
 class Phys(ctypes.Structure):

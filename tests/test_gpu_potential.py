@@ -87,8 +87,10 @@ def test_type1_parity(n, L, kernel, prec):
 @pytest.mark.parametrize("n,L,kernel,prec", [CASES[0], CASES[2], CASES[8], CASES[9]])
 def test_spread_decompositions_and_autotune(n, L, kernel, prec):
     """Every spreading work decomposition (gather blocks of 64/128 candidates x work items of
-    256..2048 candidates, and the LDS-atomic scatter) gives the oracle's type-1 sum; the
-    autotuner times them all, keeps one of them, and the plan still agrees with the oracle."""
+    256..2048 candidates from the explicit lists, 512..2048 from the neighbour bins, and the
+    LDS-atomic scatter) gives the oracle's type-1 sum; the autotuner times them all, keeps one
+    of them, and the plan still agrees with the oracle.  The whole potential is checked under
+    the neighbour-bin decomposition too (in 3D it switches the interpolation kernel)."""
     print(f"[spread decompositions] n={n} kernel={kernel} prec={prec}", flush=True)
     plan = nlf.Plan(n, L, kernel, prec=prec)
     assert plan.info.gather_available == 1
@@ -98,6 +100,8 @@ def test_spread_decompositions_and_autotune(n, L, kernel, prec):
     cd = torch.tensor(c, dtype=plan.cdtype, device="cuda")
     want = op.type1_direct(cd.cpu().numpy().astype(np.complex128), n, L, k)
     cfgs = [(nlf.SPREAD_GATHER, b, i) for b in (64, 128) for i in (256, 512, 1024, 2048)]
+    assert plan.info.bins_available == 1
+    cfgs += [(nlf.SPREAD_BINS, b, i) for b in (64, 128) for i in (512, 1024, 2048)]
     if prec == nlf.F32:
         # FP32 plans spread into an FP64 grid, which only the gather kernels fill
         with pytest.raises(nlf.NlfError):
@@ -118,6 +122,30 @@ def test_spread_decompositions_and_autotune(n, L, kernel, prec):
         plan.set_spread(nlf.SPREAD_GATHER, 96, 1024)
     with pytest.raises(nlf.NlfError):
         plan.set_spread(nlf.SPREAD_GATHER, 64, 300)
+    with pytest.raises(nlf.NlfError):
+        plan.set_spread(nlf.SPREAD_BINS, 64, 256)     # below the allocated item minimum
+    rho = _case_density(n, L, seed=11)
+    want_u = op.potential(host_input(rho, prec), n, L, kernel)
+    for mode in (nlf.SPREAD_BINS, nlf.SPREAD_GATHER):
+        plan.set_spread(mode, 64, 1024)
+        u = plan.potential(to_dev(rho, prec)).cpu().numpy().astype(np.float64)
+        assert rel_err(u, want_u) <= TOL[prec], mode
+
+
+def test_neighbour_bins_match_explicit_lists_512():
+    """At 512^2 (both decompositions available) the neighbour-bin gather and the explicit
+    candidate lists give the same potential up to FP64 rounding (the extra candidates of the
+    bins add only weights below the stencil's truncation level)."""
+    n, L = (512, 512), (16.0, 16.0)
+    print(f"[bins vs lists] n={n}", flush=True)
+    rho = _case_density(n, L, seed=5)
+    plan = nlf.Plan(n, L, nlf.COULOMB2D)
+    assert plan.info.gather_available == 1 and plan.info.bins_available == 1
+    out = {}
+    for mode in (nlf.SPREAD_GATHER, nlf.SPREAD_BINS):
+        plan.set_spread(mode, 64, 1024)
+        out[mode] = plan.potential(to_dev(rho, nlf.F64)).cpu().numpy()
+    assert rel_err(out[nlf.SPREAD_BINS], out[nlf.SPREAD_GATHER]) <= 1e-12
 
 
 def test_batch_matches_single():
