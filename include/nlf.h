@@ -54,10 +54,16 @@ extern "C" {
 #define NLF_F64 0
 #define NLF_F32 1
 
-/* Interaction kernels (Sec. 1, Eqs. 'Kernal' and 'Kernal21d').                            */
+/* Interaction kernels (Sec. 1, Eqs. 'Kernal' and 'Kernal21d'; Sec. 2, Eq. 'Kernal124d').     */
 #define NLF_COULOMB3D 1   /* U = 1/(4 pi |x|),     Uhat = 1/|k|^2, d = 3                    */
 #define NLF_COULOMB2D 2   /* U = 1/(2 pi |x|),     Uhat = 1/|k|,   d = 2                    */
 #define NLF_LAPLACE2D 3   /* U = -ln|x| / (2 pi),  Uhat = 1/|k|^2, d = 2 (Gaussian subtraction) */
+/* Confined Coulomb kernel U_Con^eps of a strongly confined 3D Schroedinger-Poisson system,
+ * d = 2 (Sec. 2.3, Eqs. 'ifft2d' and '2Dw1'): the polar quadrature of the 2D Coulomb kernel with
+ * symbol x Jacobian W1(|k|) = (2/pi) int_0^inf e^{-eps^2 |k|^2 s^2 / 2} / (1 + s^2) ds, which
+ * equals erfcx(eps |k| / sqrt 2) = e^{a^2} erfc(a) at a = eps |k| / sqrt 2 (W1(0) = 1).  The
+ * plan tabulates W1 per node on the host in FP64; opts.eps > 0 is required.               */
+#define NLF_CONFINED2D 4
 
 /* ---- plan ----------------------------------------------------------------------------- */
 typedef struct {
@@ -76,6 +82,8 @@ typedef struct {
     double sigma;    /* Laplace subtraction width                   (default 6 sqrt(2) / P)    */
     int    msp;      /* Gaussian half-width in oversampled cells    (default 12 FP64, 7 FP32)  */
     int    batch;    /* independent fields per call                 (default 1)                */
+    double eps;      /* confinement ratio of NLF_CONFINED2D, > 0     (no default; other kernels
+                        ignore it)                                                             */
 } nlf_opts;
 
 typedef struct nlf_plan nlf_plan;
@@ -91,11 +99,12 @@ typedef struct {
     long long n_half;      /* M / 2 nodes actually evaluated (the other half by symmetry)      */
     long long workspace_bytes;
     /* spreading work decomposition in use (see nlf_plan_set_spread / nlf_plan_autotune) */
-    int spread_mode;       /* NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER                       */
+    int spread_mode;       /* NLF_SPREAD_GATHER, NLF_SPREAD_SCATTER or NLF_SPREAD_BINS        */
     int spread_block;      /* candidates per block of the gather kernel (64 or 128)         */
     int spread_item;       /* candidates per work item of the gather kernel (256 .. 2048)   */
     int gather_available;  /* 1 if the plan built its gather-tile candidate lists           */
     int bins_available;    /* 1 if the neighbour-bin gather applies (grids large enough)    */
+    double eps;            /* confinement ratio (NLF_CONFINED2D), else 0                     */
 } nlf_plan_info;
 
 /* Create a plan for the potential of `kernel` on `box` (Sec. 2.1 nodes and weights, Eq.

@@ -6,6 +6,16 @@ quadrature sum approximates.  Each function states the density it belongs to.
 * 3D Coulomb, rho = exp(-(x^2+y^2+gamma^2 z^2)/sigma^2)   -- Example 2.1, Eq. 'DensGaus'
 * 2D Coulomb, rho = exp(-(x^2+gamma^2 y^2)/sigma^2)       -- Example 2.2, Eq. '2.5D-clb-exact'
 * 2D Laplace, rho = exp(-|x|^2/sigma^2)                   -- Example 2.3, Eq. 'eg-2d-Exact'
+* 2D confined Coulomb U_Con^eps (Sec. 2, Eq. 'Kernal124d'), rho = exp(-|x|^2/sigma^2) -- not in
+  the paper; derived here.  With W1(k) = |k| Uhat = erfcx(eps |k| / sqrt 2) (Eq. '2Dw1' is
+  (2/pi) int e^{-a^2 s^2}/(1+s^2) ds = erfcx(a), a standard integral) and
+  rhohat = pi sigma^2 e^{-sigma^2 k^2 / 4}, the polar form of Eq. 'ifft2d' gives
+      u(r) = (sigma^2 / 2) int_0^inf erfcx(eps k / sqrt 2) e^{-sigma^2 k^2 / 4} J0(k r) dk,
+  and at r = 0, putting the integral of W1 back and integrating over k first,
+      u(0) = sigma^2 / (2 sqrt pi) int_0^inf ds / ((1 + s^2) sqrt(c^2 + b^2 s^2)),
+  c = sigma / 2, b = eps / sqrt 2, which is arccos(b/c)/q with q = sqrt(c^2 - b^2) for c > b
+  (acosh(b/c)/q, q = sqrt(b^2 - c^2), for b > c; 1/c for b = c).  eps -> 0 gives the 2D
+  Coulomb value sqrt(pi) sigma / 2.
 * 2D Laplace, rho = exp(-x^2/a^2 - y^2/b^2)               -- not in the paper; derived from
   the heat-semigroup representation -Delta^{-1} = int_0^inf e^{t Delta} dt with the
   logarithmic far field of Sec. 2.2 (Eq. 'Poiff35a') fixing the constant:
@@ -15,7 +25,7 @@ quadrature sum approximates.  Each function states the density it belongs to.
 """
 import numpy as np
 from scipy.integrate import quad
-from scipy.special import erf, exp1, i0e
+from scipy.special import erf, erfcx, exp1, i0e, j0
 
 EULER_GAMMA = 0.57721566490153286061
 
@@ -110,3 +120,28 @@ def laplace2d_gauss_aniso(x, y, a, b):
         return v1 + v2
 
     return np.vectorize(one)(x, y)
+
+
+def confined2d_gauss_origin(sigma, eps):
+    """u(0) of the confined Coulomb kernel for rho = exp(-|x|^2/sigma^2) (module docstring)."""
+    c, b = 0.5 * sigma, eps / np.sqrt(2.0)
+    if abs(c - b) < 1e-12 * c:
+        integral = 1.0 / c
+    elif c > b:
+        q = np.sqrt(c * c - b * b)
+        integral = np.arccos(b / c) / q
+    else:
+        q = np.sqrt(b * b - c * c)
+        integral = np.arccosh(b / c) / q
+    return sigma * sigma / (2.0 * np.sqrt(np.pi)) * integral
+
+
+def confined2d_gauss(r, sigma, eps):
+    """u(r) of the confined Coulomb kernel for rho = exp(-|x|^2/sigma^2): the radial Hankel
+    integral of the module docstring by adaptive quadrature (scipy's erfcx and J0)."""
+    def one(rr):
+        f = lambda k: erfcx(eps * k / np.sqrt(2.0)) * np.exp(-0.25 * sigma * sigma * k * k) * j0(k * rr)
+        kmax = 2.0 * 40.0 ** 0.5 / sigma * 2.0          # e^{-sigma^2 k^2 / 4} < e^{-160} beyond
+        v, _ = quad(f, 0.0, kmax, epsabs=1e-17, epsrel=1e-13, limit=2000)
+        return 0.5 * sigma * sigma * v
+    return np.vectorize(one)(np.asarray(r, dtype=np.float64))

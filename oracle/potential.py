@@ -9,6 +9,9 @@ sums.  No FFT, no spreading, no blocking beyond chunking the node set:
     S_m    = rhohat(k_m)                                   Coulomb 3D / 2D  (Sec. 2.1, Eq. 'ifft')
            = [rhohat(k_m) - (m0 - i k_m . m1) e^{-sigma^2 |k_m|^2 / 2}] / |k_m|
                                                            Laplace 2D        (Sec. 2.2, Eq. 'phi2fourier')
+           = W1(|k_m|) rhohat(k_m)                         confined Coulomb 2D (Sec. 2.3, Eqs. 'ifft2d',
+                                                           '2Dw1'), W1 by adaptive Gauss-Kronrod
+                                                           quadrature of its defining integral
     rhohat(k) = (prod_i h_i) sum_j rho_j exp(-i k . x_j)   trapezoid rule for the Fourier
                                                            transform of grid data (Alg. 1, first step)
 
@@ -24,6 +27,7 @@ transform of a shifted Gaussian, adjointness of the two sums, symmetry and posit
 of the operator (tests/test_oracle_potential.py).
 """
 import numpy as np
+from scipy.integrate import quad
 from scipy.special import exp1
 
 from .quadrature import ball_nodes
@@ -33,6 +37,8 @@ EULER_GAMMA = 0.57721566490153286061
 COULOMB3D = 1   # U = 1/(4 pi |x|),   Uhat = 1/|k|^2   (Sec. 1, Eq. 'Kernal', d = 3)
 COULOMB2D = 2   # U = 1/(2 pi |x|),   Uhat = 1/|k|     (Sec. 1, Eq. 'Kernal', d = 2)
 LAPLACE2D = 3   # U = -ln|x| / (2 pi), Uhat = 1/|k|^2  (Sec. 1, Eq. 'Kernal21d', d = 2)
+CONFINED2D = 4  # U_Con^eps, Uhat = (2/pi) int_0^inf e^{-eps^2 s^2/2} / (|k|^2 + s^2) ds
+                #                                      (Sec. 2, Eq. 'Kernal124d', d = 2)
 
 _CHUNK = 2048
 
@@ -98,11 +104,39 @@ def moments(rho, n, L):
     return m0, np.array(m1)
 
 
-def symbol_coeffs(kernel, k, weight, kmag, rhohat, m0=None, m1=None, sigma=None):
-    """c_m = (2 pi)^-d weight_m S_m with S_m per kernel (module docstring)."""
+def confined_w1(kmag, eps):
+    """W1(|k|) = |k| Uhat_Con^eps(k) = (2/pi) int_0^inf e^{-eps^2 |k|^2 s^2 / 2} / (1 + s^2) ds,
+    W1(0) = 1 (Sec. 2.3, Eq. '2Dw1'), by adaptive Gauss-Kronrod quadrature (QUADPACK, as the
+    paper suggests) once per distinct |k|.  With a = eps |k| / sqrt 2 and t = a s the integral
+    is (2/pi) int_0^inf e^{-t^2} a / (a^2 + t^2) dt; for a <= 1, where that integrand is a
+    spike of width a, the same integral is taken as 1 - (2/pi) int_0^inf (1 - e^{-t^2}) a /
+    (a^2 + t^2) dt (int_0^inf ds / (1 + s^2) = pi/2 subtracted), whose integrand is smooth."""
+    kmag = np.asarray(kmag, dtype=np.float64)
+    vals = {}
+    for q in np.unique(kmag):
+        a = eps * q / np.sqrt(2.0)
+        if a == 0.0:
+            vals[q] = 1.0
+            continue
+        if a <= 1.0:
+            f = lambda t: -np.expm1(-t * t) * a / (a * a + t * t)
+            v, _ = quad(f, 0.0, np.inf, epsabs=1e-17, epsrel=1e-13, limit=400)
+            vals[q] = 1.0 - 2.0 / np.pi * v
+        else:
+            f = lambda t: np.exp(-t * t) * a / (a * a + t * t)
+            v, _ = quad(f, 0.0, np.inf, epsabs=1e-17, epsrel=1e-13, limit=400)
+            vals[q] = 2.0 / np.pi * v
+    return np.vectorize(vals.__getitem__, otypes=[np.float64])(kmag)
+
+
+def symbol_coeffs(kernel, k, weight, kmag, rhohat, m0=None, m1=None, sigma=None, w1=None):
+    """c_m = (2 pi)^-d weight_m S_m with S_m per kernel (module docstring); w1: W1(|k_m|) of the
+    confined kernel."""
     dim = k.shape[1]
     if kernel in (COULOMB3D, COULOMB2D):
         S = rhohat
+    elif kernel == CONFINED2D:
+        S = w1 * rhohat
     elif kernel == LAPLACE2D:
         kdotm1 = k @ m1
         G1hat = (m0 - 1j * kdotm1) * np.exp(-0.5 * sigma * sigma * kmag * kmag)
@@ -155,12 +189,14 @@ class DirectPotential:
     (n_0, n_0, 2 n_0).
     """
 
-    def __init__(self, n, L, kernel, P=None, n_r=None, n_theta=None, n_phi=None, sigma=None):
+    def __init__(self, n, L, kernel, P=None, n_r=None, n_theta=None, n_phi=None, sigma=None, eps=None):
         self.n = tuple(int(v) for v in n)
         self.L = tuple(float(v) for v in L)
         dim = len(self.n)
-        if (kernel == COULOMB3D and dim != 3) or (kernel in (COULOMB2D, LAPLACE2D) and dim != 2):
+        if (kernel == COULOMB3D and dim != 3) or (kernel in (COULOMB2D, LAPLACE2D, CONFINED2D) and dim != 2):
             raise ValueError("kernel/dimension mismatch")
+        if kernel == CONFINED2D and not (eps is not None and eps > 0):
+            raise ValueError("the confined kernel needs eps > 0")
         self.dim, self.kernel = dim, kernel
         self.xs, self.h = grid_axes(self.n, self.L)
         self.P = np.pi / max(self.h) if P is None else float(P)
@@ -170,6 +206,7 @@ class DirectPotential:
         self.k, self.weight, self.kmag = ball_nodes(dim, self.P, self.n_r, self.n_phi,
                                                     self.n_theta if dim == 3 else None)
         self.sigma = None
+        self.w1 = confined_w1(self.kmag, float(eps)) if kernel == CONFINED2D else None
         if kernel == LAPLACE2D:
             self.sigma = default_sigma(self.P) if sigma is None else float(sigma)
             X, Y = np.meshgrid(self.xs[0], self.xs[1], indexing="ij")
@@ -182,7 +219,7 @@ class DirectPotential:
         m0 = m1 = None
         if self.kernel == LAPLACE2D:
             m0, m1 = moments(rho, self.n, self.L)
-        c = symbol_coeffs(self.kernel, self.k, self.weight, self.kmag, rhohat, m0, m1, self.sigma)
+        c = symbol_coeffs(self.kernel, self.k, self.weight, self.kmag, rhohat, m0, m1, self.sigma, self.w1)
         uc = type1_direct(c, self.n, self.L, self.k, return_complex=True)
         u = uc.real.copy()
         if self.kernel == LAPLACE2D:
@@ -194,7 +231,7 @@ class DirectPotential:
 
 
 def potential(rho, n, L, kernel, P=None, n_r=None, n_theta=None, n_phi=None, sigma=None,
-              return_parts=False):
+              return_parts=False, eps=None):
     """One-shot direct evaluation; see `DirectPotential`."""
-    op = DirectPotential(n, L, kernel, P, n_r, n_theta, n_phi, sigma)
+    op = DirectPotential(n, L, kernel, P, n_r, n_theta, n_phi, sigma, eps)
     return op(rho, return_parts=return_parts)

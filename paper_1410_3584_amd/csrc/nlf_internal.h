@@ -69,6 +69,7 @@ struct nlf_plan {
     int n[3], Mr[3];
     double L[3], h[3];
     double P, sigma;
+    double eps = 0.0;           // confinement ratio (NLF_CONFINED2D)
     int n_r, n_theta, n_phi;
     long long N, G, M, Mh;      // grid points, oversampled grid points, nodes, half nodes
     hipStream_t stream;

@@ -160,16 +160,37 @@ static int upload_twiddles(nlf_plan* p, void** dst, int n) {
     return upload(p, dst, tw.data(), tw.size() * sizeof(T));
 }
 
+// erfcx(a) = e^{a^2} erfc(a) for a >= 0, the closed form of the confined kernel's symbol x Jacobian
+//   (2/pi) int_0^inf e^{-a^2 s^2} / (1 + s^2) ds  (Eq. '2Dw1' with a = eps |k| / sqrt 2).
+// a < 8: e^{a^2} erfc(a) with a^2 split exactly into hi + lo (fma), e^{a^2} = e^{hi} (1 + lo).
+// a >= 8: Laplace's continued fraction for the complementary error function (Abramowitz and
+// Stegun 7.1.14), sqrt(pi) erfcx(a) = 1/(a + (1/2)/(a + 1/(a + (3/2)/(a + 2/(a + ...))))), summed
+// from the 60th level up (at a >= 8 it has converged to rounding long before).
+static double erfcx_host(double a) {
+    if (a < 8.0) {
+        const double hi = a * a, lo = std::fma(a, a, -hi);
+        return std::exp(hi) * (1.0 + lo) * std::erfc(a);
+    }
+    double f = a;
+    for (int j = 60; j >= 1; --j) f = a + 0.5 * j / f;
+    return 1.0 / (std::sqrt(3.14159265358979323846) * f);
+}
+
 static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o) {
     const double pi = 3.14159265358979323846;
     p->dim = box->dim;
     p->kernel = kernel;
     if (p->dim != 2 && p->dim != 3) return set_error(NLF_EUNSUPPORTED, "dim must be 2 or 3 (got %d)", p->dim);
     if ((kernel == NLF_COULOMB3D && p->dim != 3) ||
-        ((kernel == NLF_COULOMB2D || kernel == NLF_LAPLACE2D) && p->dim != 2))
+        ((kernel == NLF_COULOMB2D || kernel == NLF_LAPLACE2D || kernel == NLF_CONFINED2D) && p->dim != 2))
         return set_error(NLF_EUNSUPPORTED, "kernel %d does not match dim %d", kernel, p->dim);
-    if (kernel < NLF_COULOMB3D || kernel > NLF_LAPLACE2D)
+    if (kernel < NLF_COULOMB3D || kernel > NLF_CONFINED2D)
         return set_error(NLF_EINVAL, "unknown kernel %d", kernel);
+    if (kernel == NLF_CONFINED2D) {
+        p->eps = o ? o->eps : 0.0;
+        if (!(p->eps > 0) || !std::isfinite(p->eps))
+            return set_error(NLF_EINVAL, "the confined Coulomb kernel needs opts.eps > 0 (got %g)", p->eps);
+    }
     p->prec = o ? o->prec : NLF_F64;
     if (p->prec != NLF_F64 && p->prec != NLF_F32) return set_error(NLF_EINVAL, "prec must be NLF_F64 or NLF_F32");
     p->batch = (o && o->batch > 0) ? o->batch : 1;
@@ -494,6 +515,9 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         if (kernel == NLF_LAPLACE2D) {
             wf[j] = 2.0 * inv2pid * p->w_host[m] / kmag;
             gk[j] = std::exp(-0.5 * p->sigma * p->sigma * kk);
+        } else if (kernel == NLF_CONFINED2D) {
+            // symbol x Jacobian of the confined kernel (Eq. '2Dw1')
+            wf[j] = 2.0 * inv2pid * p->w_host[m] * p->st2 * erfcx_host(p->eps * kmag / std::sqrt(2.0));
         } else {
             wf[j] = 2.0 * inv2pid * p->w_host[m] * p->st2;
         }
@@ -684,6 +708,7 @@ int nlf_plan_get_info(const nlf_plan* p, nlf_plan_info* info) {
     }
     info->P = p->P;
     info->sigma = p->sigma;
+    info->eps = p->eps;
     info->n_grid = p->N;
     info->n_nodes = p->M;
     info->n_half = p->Mh;

@@ -89,6 +89,22 @@ def psi0_phase_modulated(n, L, seed, n_modes=8):
     return psi / np.sqrt(dv * np.sum(np.abs(psi) ** 2))
 
 
+def honeycomb_2d(n, L):
+    """The 2D Coulomb dynamics application (Sec. 'Applications'; beta = 5 on [-32,32]^2 with
+    h = 1/16, tau = 1e-4): honeycomb external potential
+    V = 10 [cos(b1 . x) + cos(b2 . x) + cos((b1 + b2) . x)], b1 = (pi/4)(sqrt 3, 1),
+    b2 = (pi/4)(-sqrt 3, 1), and initial data psi0 = exp(-(x^2 + y^2)/2), not normalised (the
+    paper states it so).  Returns (V, psi0) on the mesh of n, L; no random draws."""
+    X, Y = mesh(n, L)
+    q = np.pi / 4.0
+    b1 = (q * np.sqrt(3.0), q)
+    b2 = (-q * np.sqrt(3.0), q)
+    V = 10.0 * (np.cos(b1[0] * X + b1[1] * Y) + np.cos(b2[0] * X + b2[1] * Y)
+                + np.cos((b1[0] + b2[0]) * X + (b1[1] + b2[1]) * Y))
+    psi0 = np.exp(-0.5 * (X * X + Y * Y)).astype(np.complex128)
+    return V, psi0
+
+
 def ground_state_batch_2d(seed, count=64, sizes=(64, 128, 256)):
     """Batched 2D ground-state instances: per instance, in this order, grid N1 uniform over
     `sizes`, beta ~ U[10,1000], gamma ~ U[0.5,2] (V = (x^2 + gamma^2 y^2)/2), box [-16,16]^2."""

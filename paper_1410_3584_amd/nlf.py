@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libnlf.so")
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
-COULOMB3D, COULOMB2D, LAPLACE2D = 1, 2, 3
+COULOMB3D, COULOMB2D, LAPLACE2D, CONFINED2D = 1, 2, 3, 4
 
 EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan_nodes",
            "nlf_potential", "nlf_type2", "nlf_type1", "nlf_ground_state", "nlf_ground_state_batch",
@@ -34,7 +34,7 @@ class Box(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("n_r", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_phi", ctypes.c_int), ("P", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("msp", ctypes.c_int), ("batch", ctypes.c_int)]
+                ("msp", ctypes.c_int), ("batch", ctypes.c_int), ("eps", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_nodes", ctypes.c_longlong), ("n_half", ctypes.c_longlong),
                 ("workspace_bytes", ctypes.c_longlong), ("spread_mode", ctypes.c_int),
                 ("spread_block", ctypes.c_int), ("spread_item", ctypes.c_int),
-                ("gather_available", ctypes.c_int), ("bins_available", ctypes.c_int)]
+                ("gather_available", ctypes.c_int), ("bins_available", ctypes.c_int),
+                ("eps", ctypes.c_double)]
 
 
 class Phys(ctypes.Structure):
@@ -143,10 +144,11 @@ def _ptr(t):
 
 
 class Plan:
-    """A potential plan (nlf_plan_create).  kernel: COULOMB3D / COULOMB2D / LAPLACE2D."""
+    """A potential plan (nlf_plan_create).  kernel: COULOMB3D / COULOMB2D / LAPLACE2D /
+    CONFINED2D (which needs eps > 0)."""
 
     def __init__(self, n, L, kernel, prec=F64, n_r=0, n_theta=0, n_phi=0, P=0.0, sigma=0.0,
-                 msp=0, batch=1, stream=None):
+                 msp=0, batch=1, stream=None, eps=0.0):
         import torch
         lib = load()
         self.torch = torch
@@ -155,7 +157,7 @@ class Plan:
         for i in range(len(n)):
             box.n[i] = int(n[i])
             box.L[i] = float(L[i])
-        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch)
+        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch, eps)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -234,6 +236,10 @@ class Plan:
         if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
             raise ValueError(f"expected a contiguous CUDA tensor of {dtype} with {numel} elements, "
                              f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+        if t.is_complex() and (t.is_conj() or t.is_neg()):
+            # torch's lazy conjugate/negative views share memory with their base: the library
+            # would read the unconjugated values
+            raise ValueError("lazy conjugate or negative view: pass t.resolve_conj() / t.resolve_neg()")
 
     def potential(self, rho, out=None):
         N = int(np.prod(self.n)) * self.batch

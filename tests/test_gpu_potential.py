@@ -58,6 +58,44 @@ def test_potential_parity(n, L, kernel, prec):
     assert rel_err(u, want) <= TOL[prec]
 
 
+@pytest.mark.parametrize("n,L,prec,eps", [((64, 64), (8.0, 8.0), nlf.F64, 0.5),
+                                          ((64, 64), (8.0, 8.0), nlf.F32, 0.5),
+                                          ((128, 64), (12.0, 6.0), nlf.F64, 2.0),
+                                          ((32, 32), (6.0, 6.0), nlf.F64, 0.05)])
+def test_confined_potential_parity(n, L, prec, eps):
+    """Confined Coulomb kernel (symbol x Jacobian erfcx(eps |k| / sqrt 2), tabulated by the plan)
+    against the oracle's potential with W1 by quadrature of its defining integral."""
+    print(f"[confined parity] n={n} prec={prec} eps={eps}", flush=True)
+    rho = _case_density(n, L, seed=9)
+    plan = nlf.Plan(n, L, nlf.CONFINED2D, prec=prec, eps=eps)
+    assert plan.info.eps == eps
+    u = plan.potential(to_dev(rho, prec)).cpu().numpy().astype(np.float64)
+    want = op.potential(host_input(rho, prec), n, L, op.CONFINED2D, eps=eps)
+    assert rel_err(u, want) <= TOL[prec]
+
+
+def test_confined_gaussian_closed_form_512():
+    """At 512^2 on [-16,16]^2 the GPU potential of exp(-|x|^2/sigma^2) matches the closed-form
+    Hankel integral of the confined kernel at sampled points (no oracle sum involved)."""
+    n, L, sigma, eps = (512, 512), (16.0, 16.0), 1.2, 0.4
+    print(f"[confined closed form] n={n}", flush=True)
+    X, Y = inputs.mesh(n, L)
+    plan = nlf.Plan(n, L, nlf.CONFINED2D, eps=eps)
+    u = plan.potential(to_dev(np.exp(-(X * X + Y * Y) / (sigma * sigma)), nlf.F64)).cpu().numpy()
+    u0 = cf.confined2d_gauss_origin(sigma, eps)
+    assert abs(u[256, 256] - u0) < 1e-11 * u0
+    idx = [(256, 300), (100, 256), (40, 450), (0, 0), (500, 7)]
+    want = cf.confined2d_gauss(np.array([np.hypot(X[i], Y[i]) for i in idx]), sigma, eps)
+    assert np.max(np.abs(np.array([u[i] for i in idx]) - want)) < 1e-11 * u0
+
+
+def test_confined_rejects_missing_eps():
+    with pytest.raises(nlf.NlfError):
+        nlf.Plan((32, 32), (6.0, 6.0), nlf.CONFINED2D)
+    with pytest.raises(nlf.NlfError):
+        nlf.Plan((16, 16, 16), (6.0, 6.0, 6.0), nlf.CONFINED2D, eps=0.5)
+
+
 @pytest.mark.parametrize("n,L,kernel,prec", [CASES[0], CASES[2], CASES[8], CASES[10]])
 def test_type2_parity(n, L, kernel, prec):
     print(f"[type2 parity] n={n} kernel={kernel} prec={prec}", flush=True)

@@ -48,6 +48,21 @@ def test_gs_parity_with_oracle(kernel, beta):
         assert abs(st[0][key] - st_o[key]) < 1e-10 * max(1.0, abs(st_o[key])), key
 
 
+def test_gs_confined_coulomb_parity_with_oracle():
+    """The confined Coulomb kernel (eps = 0.5) in the ground-state flow: same states and energies
+    as the oracle's flow with its quadrature-W1 potential."""
+    print("[gs parity] confined eps=0.5", flush=True)
+    n, L, beta, eps = (64, 64), (8.0, 8.0), 8.0, 0.5
+    plan = nlf.Plan(n, L, nlf.CONFINED2D, eps=eps)
+    psi, st, status = plan.ground_state(beta, (1.0, 2.0), tau=0.5, eps0=1e-11, check_every=1)
+    assert status == nlf.OK
+    pot = op.DirectPotential(n, L, op.CONFINED2D, eps=eps)
+    phi_o, st_o = so.ground_state(n, L, op.CONFINED2D, beta, (1.0, 2.0), tau=0.5, eps0=1e-11, pot=pot)
+    assert rel_err(psi.cpu().numpy(), phi_o) < 1e-9
+    for key in ("E", "mu", "Ekin", "Epot", "Eint"):
+        assert abs(st[0][key] - st_o[key]) < 1e-10 * max(1.0, abs(st_o[key])), key
+
+
 @pytest.mark.parametrize("table,kernel", [("gs_energies_2d_coulomb.txt", nlf.COULOMB2D),
                                           ("gs_energies_2d_poisson.txt", nlf.LAPLACE2D)])
 def test_gs_paper_energies_2d_h8(table, kernel):
@@ -290,3 +305,45 @@ def test_evolve_batch_equals_single():
         psi = torch.tensor(p0[i], dtype=torch.complex128, device="cuda")
         ps.evolve(psi, beta, g, 1e-2, 8)
         assert rel_err(psib[i].cpu().numpy(), psi.cpu().numpy()) < 1e-13
+
+
+# ---- honeycomb dynamics (Sec. 'Applications') -------------------------------------------------
+
+def test_honeycomb_dynamics_parity_with_oracle():
+    """2D Coulomb, beta = 5, honeycomb external potential, fourth-order splitting: the GPU state
+    and its (mass, energy) agree with the oracle's time splitting on a 64^2 grid of [-8,8]^2."""
+    n, L = (64, 64), (8.0, 8.0)
+    print(f"[honeycomb parity] n={n}", flush=True)
+    V, psi0 = inputs.honeycomb_2d(n, L)
+    plan = nlf.Plan(n, L, nlf.COULOMB2D)
+    psi = torch.tensor(psi0, dtype=torch.complex128, device="cuda")
+    diag = plan.evolve(psi, 5.0, (1.0, 1.0), 1e-3, 6, order=4, diag_every=3,
+                       V=torch.tensor(V, device="cuda"))
+    want, dg = so.evolve(psi0, n, L, nlf.COULOMB2D, 5.0, (1.0, 1.0), 1e-3, 6, order=4, V=V, diag_every=3)
+    assert rel_err(psi.cpu().numpy(), want) < 1e-10
+    assert np.max(np.abs(diag[:, 0, :] - np.array(dg))) < 1e-10 * np.max(np.abs(np.array(dg)))
+
+
+def test_honeycomb_dynamics_full_size_time_reversal():
+    """The paper's honeycomb run at its size (1024^2 grid of [-32,32]^2, h = 1/16, tau = 1e-4,
+    fourth-order splitting).  The splitting step is time-symmetric and the equation is
+    time-reversible (conj psi(-t) solves it), so N steps, conjugation, N steps and conjugation
+    return psi0 up to rounding; mass is conserved to rounding and energy to O(tau^4)."""
+    n, L = (1024, 1024), (32.0, 32.0)
+    print(f"[honeycomb full size] n={n}", flush=True)
+    V, psi0 = inputs.honeycomb_2d(n, L)
+    plan = nlf.Plan(n, L, nlf.COULOMB2D)
+    Vd = torch.tensor(V, device="cuda")
+    psi = torch.tensor(psi0, dtype=torch.complex128, device="cuda")
+    diag = plan.evolve(psi, 5.0, (1.0, 1.0), 1e-4, 20, order=4, diag_every=10, V=Vd)
+    moved = np.max(np.abs(psi.cpu().numpy() - psi0))
+    assert moved > 1e-4                                   # the state did evolve
+    mass, en = diag[:, 0, 0], diag[:, 0, 1]
+    assert np.max(np.abs(mass - np.pi)) < 1e-11 * np.pi   # |psi0|^2 integrates to pi
+    assert np.max(np.abs(en - en[0])) < 1e-8 * abs(en[0])
+    with pytest.raises(ValueError):          # a lazy conjugate view is refused, not misread
+        plan.evolve(psi.conj(), 5.0, (1.0, 1.0), 1e-4, 1, order=4, V=Vd)
+    psi = torch.conj_physical(psi)
+    plan.evolve(psi, 5.0, (1.0, 1.0), 1e-4, 20, order=4, V=Vd)
+    back = np.conj(psi.cpu().numpy())
+    assert np.max(np.abs(back - psi0)) < 1e-10

@@ -174,3 +174,54 @@ def test_laplace2d_sigma_invariance():
     # the printed sigma = 6/P leaves a Gaussian tail e^{-18} outside the ball: visible at 1e-9
     u3 = op.potential(rho, n, L, op.LAPLACE2D, sigma=6.0 / P)
     assert 1e-11 < np.max(np.abs(u1 - u3)) / np.max(np.abs(u1)) < 1e-6
+
+
+# ---- confined Coulomb kernel (Sec. 2, Eq. 'Kernal124d'; Sec. 2.3, Eqs. 'ifft2d', '2Dw1') ----------
+
+def test_confined_w1_quadrature_equals_erfcx_and_asymptotes():
+    """The oracle's W1 (Gauss-Kronrod quadrature of Eq. '2Dw1') equals erfcx(eps |k| / sqrt 2),
+    the closed form of that integral, is 1 at k = 0, and follows the paper's limits
+    Uhat ~ 1/|k| (|k| -> 0) and Uhat ~ sqrt(2) / (sqrt(pi) eps |k|^2) (|k| -> inf)."""
+    from scipy.special import erfcx
+    eps = 0.3
+    k = np.concatenate([[0.0, 1e-8, 1e-3], np.geomspace(0.01, 3e4, 40)])
+    w1 = op.confined_w1(k, eps)
+    want = erfcx(eps * k / np.sqrt(2.0))
+    assert np.max(np.abs(w1 / want - 1.0)) < 1e-13
+    assert w1[0] == 1.0 and abs(w1[1] - 1.0) < 1e-8
+    big = k > 1e4
+    asym = np.sqrt(2.0) / (np.sqrt(np.pi) * eps * k[big])     # |k| Uhat at large |k|
+    assert np.max(np.abs(w1[big] / asym - 1.0)) < 1e-6
+
+
+@pytest.mark.parametrize("sigma2,eps", [(1.2, 0.1), (1.2, 1.0), (2.0, 3.0)])
+def test_confined2d_gaussian_closed_form(sigma2, eps):
+    """rho = exp(-|x|^2/sigma^2) on [-8,8]^2, h = 1/4: the oracle's potential equals the Hankel
+    integral of the Gaussian (erfcx and J0, independent of the oracle's quadrature W1) at
+    sampled points, and at the origin the elementary closed form; both derivations of u(0)
+    agree with each other."""
+    n, L = (64, 64), (8.0, 8.0)
+    sigma = np.sqrt(sigma2)
+    (X, Y), _ = _grid(n, L)
+    u = op.potential(np.exp(-(X * X + Y * Y) / sigma2), n, L, op.CONFINED2D, eps=eps)
+    u0 = cf.confined2d_gauss_origin(sigma, eps)
+    assert abs(float(cf.confined2d_gauss(0.0, sigma, eps)) - u0) < 1e-13 * u0
+    assert abs(u[32, 32] - u0) < 1e-13 * u0
+    idx = [(40, 32), (32, 50), (10, 20), (0, 0), (60, 5)]
+    want = cf.confined2d_gauss(np.array([np.hypot(X[i], Y[i]) for i in idx]), sigma, eps)
+    got = np.array([u[i] for i in idx])
+    assert np.max(np.abs(got - want)) < 1e-12 * u0
+
+
+def test_confined2d_small_eps_is_coulomb2d():
+    """eps -> 0 takes U_Con^eps to the 2D Coulomb kernel (W1 -> 1): the two
+    oracle potentials agree to rounding at eps = 1e-16 (W1 = 1 - O(eps |k|)), and at eps = 1e-3
+    they differ by O(eps)."""
+    n, L = (32, 32), (6.0, 6.0)
+    rho, _ = inputs.density_2d_bumps(n, L, seed=3, n_bumps=3)
+    uc = op.potential(rho, n, L, op.COULOMB2D)
+    u0 = op.potential(rho, n, L, op.CONFINED2D, eps=1e-16)
+    u3 = op.potential(rho, n, L, op.CONFINED2D, eps=1e-3)
+    assert np.max(np.abs(u0 - uc)) < 1e-14 * np.max(np.abs(uc))
+    d = np.max(np.abs(u3 - uc)) / np.max(np.abs(uc))
+    assert 1e-5 < d < 1e-2
