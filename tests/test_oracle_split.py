@@ -1,0 +1,67 @@
+"""Pins for the oracle's split evaluation of the 3D Coulomb potential (Eq. '3.9'): each part
+against a closed form it must reproduce, the sum against Example 2.1's closed form, and the
+independence of the sum from the partition's width."""
+import numpy as np
+import pytest
+from scipy.special import erf
+
+from oracle import closed_forms as cf
+from oracle import potential as op
+from oracle import split as sp
+
+
+def _gauss(n, L, sigma):
+    xs, _ = op.grid_axes(n, L)
+    X, Y, Z = np.meshgrid(*xs, indexing="ij")
+    R = np.sqrt(X * X + Y * Y + Z * Z)
+    return R, np.exp(-R * R / (sigma * sigma))
+
+
+def _i2_closed(R, sigma, a):
+    """I2 = U2 * rho with U2 = erf(sqrt(a) r / 2) / (4 pi r), the Coulomb potential of the unit
+    Gaussian of width s = 2 / sqrt(a); for rho = exp(-r^2/sigma^2) = (pi sigma^2)^{3/2} times the
+    unit Gaussian of width sigma, the two Gaussians convolve to width S = sqrt(sigma^2 + s^2):
+    I2 = sqrt(pi) sigma^3 erf(r/S) / (4 r), sigma^3 / (2 S) at r = 0."""
+    S = np.sqrt(sigma * sigma + 4.0 / a)
+    out = np.empty_like(R)
+    nz = R > 0
+    out[nz] = np.sqrt(np.pi) * sigma ** 3 * erf(R[nz] / S) / (4.0 * R[nz])
+    out[~nz] = sigma ** 3 / (2.0 * S)
+    return out
+
+
+def test_split_parts_and_sum_closed_forms():
+    """rho = exp(-|x|^2/1.5^2) on a 32^3 grid of [-8,8]^3 (Example 2.1's setting): I2 is the
+    potential of the Gaussian blurred by the partition's width, I1 the remainder, and the sum is
+    Example 2.1's sigma^3 sqrt(pi) erf(r/sigma) / (4 r) with no ball-truncation floor (the plain
+    ball quadrature stops at erfc(sigma P / 2) ~ 2.6e-11 here)."""
+    n, L, sigma = (32,) * 3, (8.0,) * 3, 1.5
+    R, rho = _gauss(n, L, sigma)
+    u, parts = sp.split_potential(rho, n, L, return_parts=True)
+    ue = cf.coulomb3d_gauss(R, sigma)
+    i2 = _i2_closed(R, sigma, parts["a"])
+    scale = ue.max()
+    assert np.max(np.abs(parts["I2"] - i2)) < 1e-12 * scale
+    assert np.max(np.abs(parts["I1"] - (ue - i2))) < 1e-12 * scale
+    assert np.max(np.abs(u - ue)) < 1e-12 * scale
+    # the partition puts a visible share in each part
+    assert 0.1 < parts["I2"].max() / scale < 0.9
+
+
+def test_split_sum_independent_of_partition_width():
+    """Changing a moves weight between I1 and I2 but not their sum (an off-centre density, so
+    that the first moments are nonzero)."""
+    n, L = (32,) * 3, (8.0,) * 3
+    xs, _ = op.grid_axes(n, L)
+    X, Y, Z = np.meshgrid(*xs, indexing="ij")
+    rho = np.exp(-((X - 1.5) ** 2 + (Y + 1.0) ** 2 + 2.0 * Z ** 2) / 2.0)
+    a0 = sp.split_params(n, L)["a"]
+    u0, p0 = sp.split_potential(rho, n, L, return_parts=True)
+    u1, p1 = sp.split_potential(rho, n, L, a=0.8 * a0, return_parts=True)
+    assert np.max(np.abs(u0 - u1)) < 1e-11 * np.max(np.abs(u0))
+    assert np.max(np.abs(p0["I1"] - p1["I1"])) > 1e-3 * np.max(np.abs(u0))
+
+
+def test_split_rejects_coarse_grid():
+    with pytest.raises(ValueError):
+        sp.split_params((16,) * 3, (8.0,) * 3)
