@@ -84,7 +84,25 @@ typedef struct {
     int    batch;    /* independent fields per call                 (default 1)                */
     double eps;      /* confinement ratio of NLF_CONFINED2D, > 0     (no default; other kernels
                         ignore it)                                                             */
+    int    split;    /* NLF_COULOMB3D only: nonzero evaluates the split form of Sec. 2.1,
+                        Eq. '3.9', see below                                                    */
+    double split_a;  /* width a of the partition p(k) = e^{-|k|^2/a}  (default (5.5/min L_i)^2) */
 } nlf_opts;
+
+/* Split evaluation (Sec. 2.1, Eq. '3.9', Fig. 'fig3.1'; opts.split != 0, 3D Coulomb only):
+ *   u = I1 + I2,  I1 = (2 pi)^-3 int_D e^{ik.x} (1 - p(k)) / |k|^2 rhohat dk  over the cube
+ *   D = prod [-pi/h_i, pi/h_i) of the grid's frequencies, by the trapezoid rule on the lattice of
+ *   the zero-padded FFT (a cyclic convolution: forward FFT of the padded density, a multiply by
+ *   the smooth w = (1 - p)/|k|^2 (w(0) = 1/a), inverse FFT); and
+ *   I2 = (2 pi)^-3 int_{|k| <= P2} e^{ik.x} p(k) rhohat d|k| dmu dphi  by the NUFFT path of this
+ *   library on the small ball P2 = sqrt(34.5 a) (p(P2) ~ 1e-15), whose node count does not grow
+ *   with the grid.  The default a puts I1's kernel erfc(sqrt(a) r/2)/(4 pi r) at erfc(5.5) at the
+ *   nearest periodic image.  n_r, n_theta, n_phi set the ball's rule (default
+ *   ceil(P2 D/2) + 8, the same, twice that; D = 2 |L| the box diameter); P and sigma must be 0.
+ *   Needs pi / max h_i >= P2 (NLF_EUNSUPPORTED otherwise, e.g. 16^3 on [-8,8]^3).  On a split
+ *   plan nlf_type2, nlf_type1, nlf_plan_nodes and the spreading controls act on the ball's
+ *   nodes; stage times add the ball's stages to I1's (its forward FFT under FFT_FWD, the
+ *   multiply and inverse FFT under FFT_INV).                                                  */
 
 typedef struct nlf_plan nlf_plan;
 
@@ -105,6 +123,8 @@ typedef struct {
     int gather_available;  /* 1 if the plan built its gather-tile candidate lists           */
     int bins_available;    /* 1 if the neighbour-bin gather applies (grids large enough)    */
     double eps;            /* confinement ratio (NLF_CONFINED2D), else 0                     */
+    int split;             /* 1 for a split plan; then n_nodes/n_half/spread_* are the ball's */
+    double split_a, split_P2;   /* partition width a and ball radius P2 (split plans)     */
 } nlf_plan_info;
 
 /* Create a plan for the potential of `kernel` on `box` (Sec. 2.1 nodes and weights, Eq.

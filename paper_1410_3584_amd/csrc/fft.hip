@@ -154,6 +154,7 @@ struct RowsArgs {
     const double* dec0; const double* dec1; const double* dec2;  // 1/c_g per axis (mapped modes)
     const void* tw;
     double post;           // output scale (STORE_U)
+    int accum;             // STORE_U: add to u instead of overwriting it
     // 2D Laplace: u += m0 u11 - m1 . u12 (Sec. 2.2, Eqs. 'phi1_exct', 'phi12_ext')
     int add_u1;
     const double* mom;     // [batch][4]: m0, m1x, m1y
@@ -287,7 +288,8 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
                 double f = (r2 > 0) ? expm1(-r2 * inv2s2) / (2.0 * 3.14159265358979323846 * r2) : 0.0;
                 val += m0 * a.u11[(long long)j0 * ndl + j] - (m1x * f * x + m1y * f * y);
             }
-            u[(long long)(line0 + l) * ndl + j] = (TIO)val;
+            TIO* dst = u + (long long)(line0 + l) * ndl + j;
+            *dst = a.accum ? (TIO)((double)*dst + val) : (TIO)val;
         }
     }
 }
@@ -522,6 +524,7 @@ static int type1_inverse_t(nlf_plan* p, void* u, bool add_u1) {
     r.dec2 = p->dec[2];
     r.tw = p->tw_t1[d - 1];
     r.post = p->post;
+    r.accum = p->split;   // a split's I1 adds to the I2 already in u
     r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
     r.add_u1 = add_u1 ? 1 : 0;
     r.mom = p->mom;

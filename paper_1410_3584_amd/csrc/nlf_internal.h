@@ -70,6 +70,11 @@ struct nlf_plan {
     double L[3], h[3];
     double P, sigma;
     double eps = 0.0;           // confinement ratio (NLF_CONFINED2D)
+    // split evaluation (3D Coulomb): I1 by this plan's FFTs, I2 by the ball plan `sub`
+    int split = 0;
+    double split_a = 0.0, split_P2 = 0.0;
+    nlf_plan* sub = nullptr;
+    double pweight_a = 0.0;     // ball plan of a split: node weights times exp(-|k|^2 / a)
     int n_r, n_theta, n_phi;
     long long N, G, M, Mh;      // grid points, oversampled grid points, nodes, half nodes
     hipStream_t stream;

@@ -1050,7 +1050,54 @@ int fold_c(nlf_plan* p, const void* c) {
         NLF_TRY(stage_end(p, id, mk_));      \
     } while (0)
 
+// I1 of the split evaluation: the padded spectrum times w(k) = (1 - e^{-|k|^2/a}) / |k|^2, w(0) = 1/a,
+// at the lattice frequency of each cell (index c -> c or c - Mr, times dk = 2 pi / (Mr h)), in place.
+template <typename T>
+__global__ void k_split_w(V2<T>* __restrict__ grid, long long G, int Mr0, int Mr1, int Mr2, double dk0, double dk1,
+                          double dk2, double inva) {
+    V2<T>* g = grid + (long long)blockIdx.y * G;
+    const long long plane = (long long)Mr1 * Mr2;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < G; i += (long long)gridDim.x * blockDim.x) {
+        const int c0 = (int)(i / plane);
+        const int r = (int)(i - c0 * plane);
+        const int c1 = r / Mr2, c2 = r - c1 * Mr2;
+        const double k0 = (c0 < Mr0 / 2 ? c0 : c0 - Mr0) * dk0;
+        const double k1 = (c1 < Mr1 / 2 ? c1 : c1 - Mr1) * dk1;
+        const double k2 = (c2 < Mr2 / 2 ? c2 : c2 - Mr2) * dk2;
+        const double kk = k0 * k0 + k1 * k1 + k2 * k2;
+        const double w = kk > 0.0 ? -expm1(-kk * inva) / kk : inva;
+        V2<T> v = g[i];
+        v.x = (T)((double)v.x * w);
+        v.y = (T)((double)v.y * w);
+        g[i] = v;
+    }
+}
+
+static int split_w(nlf_plan* p) {
+    double dk[3];
+    for (int i = 0; i < 3; ++i) dk[i] = 2.0 * 3.14159265358979323846 / (p->Mr[i] * p->h[i]);
+    dim3 grid((unsigned)std::min<long long>((p->G + 255) / 256, 16384), p->batch);
+    if (p->prec == NLF_F64)
+        hipLaunchKernelGGL((k_split_w<double>), grid, dim3(256), 0, p->stream, (double2*)p->grid_a, p->G, p->Mr[0],
+                           p->Mr[1], p->Mr[2], dk[0], dk[1], dk[2], 1.0 / p->split_a);
+    else
+        hipLaunchKernelGGL((k_split_w<float>), grid, dim3(256), 0, p->stream, (float2*)p->grid_a, p->G, p->Mr[0],
+                           p->Mr[1], p->Mr[2], dk[0], dk[1], dk[2], 1.0 / p->split_a);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
 int potential(nlf_plan* p, const void* rho, void* u) {
+    if (p->sub) {
+        // split (Eq. '3.9'): I2 by the ball plan writes u, then I1 = the cyclic convolution of the
+        // padded density with w adds to it; the ball plan follows this plan's current stream
+        p->sub->stream = p->stream;
+        NLF_TRY(potential(p->sub, rho, u));
+        NLF_STAGE(p, NLF_STAGE_FFT_FWD, fft_type2_forward(p, rho));
+        NLF_STAGE(p, NLF_STAGE_FFT_INV, split_w(p));
+        NLF_STAGE(p, NLF_STAGE_FFT_INV, fft_type1_inverse(p, u, false));
+        return NLF_OK;
+    }
     const bool lap = p->kernel == NLF_LAPLACE2D;   // moments m0, m1: computed by the forward FFT
     NLF_STAGE(p, NLF_STAGE_FFT_FWD, fft_type2_forward(p, rho));
     // 2D: the interpolation kernel also clears the spreading grid (the zero stage then reports 0)
@@ -1079,6 +1126,10 @@ int nlf_potential(nlf_plan* p, const void* rho, void* u) {
 int nlf_type2(nlf_plan* p, const void* rho, void* rhohat) {
     clear_error();
     if (!p || !rho || !rhohat) return set_error(NLF_EINVAL, "plan, rho and rhohat must not be NULL");
+    if (p->sub) {   // the ball of a split
+        p->sub->stream = p->stream;
+        return nlf_type2(p->sub, rho, rhohat);
+    }
     NLF_TRY(fft_type2_forward(p, rho));
     return interp(p, MODE_TYPE2, rhohat, false);
 }
@@ -1086,6 +1137,10 @@ int nlf_type2(nlf_plan* p, const void* rho, void* rhohat) {
 int nlf_type1(nlf_plan* p, const void* c, void* u) {
     clear_error();
     if (!p || !c || !u) return set_error(NLF_EINVAL, "plan, c and u must not be NULL");
+    if (p->sub) {   // the ball of a split
+        p->sub->stream = p->stream;
+        return nlf_type1(p->sub, c, u);
+    }
     NLF_TRY(fold_c(p, c));
     NLF_TRY(spread(p));
     return fft_type1_inverse(p, u, false);
@@ -1094,6 +1149,7 @@ int nlf_type1(nlf_plan* p, const void* c, void* u) {
 int nlf_plan_set_spread(nlf_plan* p, int mode, int block, int item) {
     clear_error();
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (p->sub) return nlf_plan_set_spread(p->sub, mode, block, item);   // the ball of a split
     if (mode != NLF_SPREAD_GATHER && mode != NLF_SPREAD_SCATTER && mode != NLF_SPREAD_BINS)
         return set_error(NLF_EINVAL, "spread mode must be NLF_SPREAD_GATHER, _SCATTER or _BINS");
     if (mode == NLF_SPREAD_SCATTER) {
@@ -1119,6 +1175,10 @@ int nlf_plan_set_spread(nlf_plan* p, int mode, int block, int item) {
 int nlf_plan_autotune(nlf_plan* p, int reps, double* best_ms) {
     clear_error();
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (p->sub) {   // the ball of a split
+        p->sub->stream = p->stream;
+        return nlf_plan_autotune(p->sub, reps, best_ms);
+    }
     if (reps <= 0) reps = 5;
     struct Cfg { int mode, block, item; };
     std::vector<Cfg> cfgs;

@@ -176,6 +176,66 @@ static double erfcx_host(double a) {
     return 1.0 / (std::sqrt(3.14159265358979323846) * f);
 }
 
+static int plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* stream, double pweight_a,
+                       nlf_plan** out);
+static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o);
+
+// Split evaluation (Sec. 2.1, Eq. '3.9'), 3D Coulomb.  This plan keeps only what I1 needs: the
+// oversampled grid, its twiddles and unit pre/post-correction tables (so that the type-2 and
+// type-1 FFT passes become the plain zero-padded forward FFT and the truncating inverse FFT of a
+// cyclic convolution).  I2 is a ball plan (`sub`) of radius P2 whose node weights carry p(k).
+static int build_split(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o) {
+    if (kernel != NLF_COULOMB3D) return set_error(NLF_EUNSUPPORTED, "the split evaluation is for NLF_COULOMB3D");
+    if (o->P > 0 || o->sigma > 0) return set_error(NLF_EINVAL, "a split plan takes no P or sigma");
+    double Lmin = p->L[0], D2 = 0;
+    for (int i = 0; i < 3; ++i) {
+        Lmin = std::min(Lmin, p->L[i]);
+        D2 += 4.0 * p->L[i] * p->L[i];
+    }
+    p->split = 1;
+    p->split_a = (o->split_a > 0) ? o->split_a : (5.5 / Lmin) * (5.5 / Lmin);
+    p->split_P2 = std::sqrt(34.5 * p->split_a);
+    if (p->split_P2 > p->P * (1 + 1e-12))
+        return set_error(NLF_EUNSUPPORTED, "grid too coarse for the split: pi/max(h) = %g < P2 = sqrt(34.5 a) = %g",
+                         p->P, p->split_P2);
+    const int nr = (int)std::ceil(0.5 * p->split_P2 * std::sqrt(D2)) + 8;
+    nlf_opts so = *o;
+    so.split = 0;
+    so.split_a = 0;
+    so.P = p->split_P2;
+    so.n_r = o->n_r > 0 ? o->n_r : nr;
+    so.n_theta = o->n_theta > 0 ? o->n_theta : nr;
+    so.n_phi = o->n_phi > 0 ? o->n_phi : 2 * nr;
+    NLF_TRY(plan_create(box, kernel, &so, p->stream, p->split_a, &p->sub));
+    p->n_r = p->sub->n_r;
+    p->n_theta = p->sub->n_theta;
+    p->n_phi = p->sub->n_phi;
+    p->M = p->sub->M;
+    p->Mh = p->sub->Mh;
+
+    const size_t es = elem_size(p->prec);
+    p->t1_prec = p->prec;
+    NLF_TRY(dev_alloc(p, &p->grid_a, (size_t)p->batch * p->G * es));
+    p->grid_b = p->grid_a;   // the inverse transform runs in place on the multiplied spectrum
+    for (int i = 0; i < p->dim; ++i) {
+        std::vector<double> one(p->n[i], 1.0);
+        NLF_TRY(upload(p, (void**)&p->dec[i], one.data(), one.size() * sizeof(double)));
+        if (p->prec == NLF_F64) {
+            NLF_TRY(upload_twiddles<double>(p, &p->tw_big[i], p->Mr[i]));
+            NLF_TRY(upload_twiddles<double>(p, &p->tw_small[i], p->n[i]));
+        } else {
+            NLF_TRY(upload_twiddles<float>(p, &p->tw_big[i], p->Mr[i]));
+            NLF_TRY(upload_twiddles<float>(p, &p->tw_small[i], p->n[i]));
+        }
+        p->tw_t1[i] = p->tw_big[i];
+    }
+    NLF_TRY(dev_alloc(p, (void**)&p->mom, (size_t)p->batch * 4 * sizeof(double)));
+    p->red_bytes = (size_t)p->batch * 1024 * 8 * sizeof(double);
+    NLF_TRY(dev_alloc(p, (void**)&p->red, p->red_bytes));
+    p->spread_mode = p->sub->spread_mode;
+    return NLF_OK;
+}
+
 static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o) {
     const double pi = 3.14159265358979323846;
     p->dim = box->dim;
@@ -248,6 +308,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         p->tile[i] = std::min(t, p->Mr[i]);
         p->window[i] = (i < p->dim) ? p->tile[i] + 2 * p->msp - 1 : 1;
     }
+    if (o && o->split) return build_split(p, box, kernel, o);
 
     // ---- quadrature nodes (canonical order) -----------------------------------------------
     std::vector<double> tr, wr, mu, wmu;
@@ -521,6 +582,8 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         } else {
             wf[j] = 2.0 * inv2pid * p->w_host[m] * p->st2;
         }
+        // ball of a split evaluation: the partition p(k) = exp(-|k|^2 / a) rides on the weight
+        if (p->pweight_a > 0) wf[j] *= std::exp(-kk / p->pweight_a);
     }
 
     // ---- device buffers ------------------------------------------------------------------------
@@ -583,6 +646,33 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     return NLF_OK;
 }
 
+static int plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* stream, double pweight_a,
+                       nlf_plan** out) {
+    *out = nullptr;
+    nlf_plan* p = new (std::nothrow) nlf_plan();
+    if (!p) return set_error(NLF_ENOMEM, "host allocation of the plan failed");
+    p->stream = (hipStream_t)stream;
+    p->box_copy = *box;
+    if (opts) p->opts_copy = *opts;
+    p->pweight_a = pweight_a;
+    int st;
+    try {
+        st = build(p, box, kernel, opts);
+    } catch (const std::bad_alloc&) {
+        st = set_error(NLF_ENOMEM, "host allocation failed while building the plan");
+    } catch (...) {
+        st = set_error(NLF_EINVAL, "unexpected failure while building the plan");
+    }
+    if (st != NLF_OK) {
+        if (p->sub) nlf_plan_destroy(p->sub);
+        for (void* q : p->owned) (void)hipFree(q);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return NLF_OK;
+}
+
 static int next_event(nlf_plan* p, size_t* idx) {
     if (p->ev_used == p->ev_pool.size()) {
         hipEvent_t e;
@@ -633,27 +723,7 @@ extern "C" {
 int nlf_plan_create(const nlf_box* box, int kernel, const nlf_opts* opts, void* stream, nlf_plan** out) {
     clear_error();
     if (!box || !out) return set_error(NLF_EINVAL, "box and out must not be NULL");
-    *out = nullptr;
-    nlf_plan* p = new (std::nothrow) nlf_plan();
-    if (!p) return set_error(NLF_ENOMEM, "host allocation of the plan failed");
-    p->stream = (hipStream_t)stream;
-    p->box_copy = *box;
-    if (opts) p->opts_copy = *opts;
-    int st;
-    try {
-        st = build(p, box, kernel, opts);
-    } catch (const std::bad_alloc&) {
-        st = set_error(NLF_ENOMEM, "host allocation failed while building the plan");
-    } catch (...) {
-        st = set_error(NLF_EINVAL, "unexpected failure while building the plan");
-    }
-    if (st != NLF_OK) {
-        for (void* q : p->owned) (void)hipFree(q);
-        delete p;
-        return st;
-    }
-    *out = p;
-    return NLF_OK;
+    return plan_create(box, kernel, opts, stream, 0.0, out);
 }
 
 int nlf_plan_set_profiling(nlf_plan* p, int on) {
@@ -661,6 +731,7 @@ int nlf_plan_set_profiling(nlf_plan* p, int on) {
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
     if (!on) NLF_TRY(drain_events(p));
     p->profiling = on ? 1 : 0;
+    if (p->sub) return nlf_plan_set_profiling(p->sub, on);
     return NLF_OK;
 }
 
@@ -668,9 +739,12 @@ int nlf_plan_stage_times(nlf_plan* p, double* ms, long long* counts, int reset) 
     clear_error();
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
     NLF_TRY(drain_events(p));
+    double sms[NLF_NSTAGES] = {0};
+    long long scnt[NLF_NSTAGES] = {0};
+    if (p->sub) NLF_TRY(nlf_plan_stage_times(p->sub, sms, scnt, reset));   // the ball of a split
     for (int i = 0; i < NLF_NSTAGES; ++i) {
-        if (ms) ms[i] = p->stage_ms[i];
-        if (counts) counts[i] = p->stage_cnt[i];
+        if (ms) ms[i] = p->stage_ms[i] + sms[i];
+        if (counts) counts[i] = p->stage_cnt[i] + scnt[i];
         if (reset) { p->stage_ms[i] = 0; p->stage_cnt[i] = 0; }
     }
     return NLF_OK;
@@ -683,6 +757,7 @@ int nlf_plan_destroy(nlf_plan* p) {
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
     if (p->sws && p->sws_free) p->sws_free(p->sws);
     if (p->twin) nlf_plan_destroy(p->twin);
+    if (p->sub) nlf_plan_destroy(p->sub);
     if (p->own_stream) {
         (void)hipStreamSynchronize(p->own_stream);
         (void)hipStreamDestroy(p->own_stream);
@@ -718,12 +793,25 @@ int nlf_plan_get_info(const nlf_plan* p, nlf_plan_info* info) {
     info->spread_item = p->item_cap;
     info->gather_available = p->use_gather;
     info->bins_available = p->gather_impl_ok;
+    if (p->sub) {
+        info->split = 1;
+        info->split_a = p->split_a;
+        info->split_P2 = p->split_P2;
+        info->msp = p->sub->msp;
+        info->spread_mode = p->sub->spread_mode;
+        info->spread_block = p->sub->spread_kc;
+        info->spread_item = p->sub->item_cap;
+        info->gather_available = p->sub->use_gather;
+        info->bins_available = p->sub->gather_impl_ok;
+        info->workspace_bytes += p->sub->workspace_bytes;
+    }
     return NLF_OK;
 }
 
 int nlf_plan_nodes(const nlf_plan* p, double* k_host, double* w_host) {
     clear_error();
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
+    if (p->sub) return nlf_plan_nodes(p->sub, k_host, w_host);   // the ball of a split
     if (k_host) std::memcpy(k_host, p->k_host.data(), p->k_host.size() * sizeof(double));
     if (w_host) std::memcpy(w_host, p->w_host.data(), p->w_host.size() * sizeof(double));
     return NLF_OK;

@@ -34,7 +34,8 @@ class Box(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("n_r", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_phi", ctypes.c_int), ("P", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("msp", ctypes.c_int), ("batch", ctypes.c_int), ("eps", ctypes.c_double)]
+                ("msp", ctypes.c_int), ("batch", ctypes.c_int), ("eps", ctypes.c_double),
+                ("split", ctypes.c_int), ("split_a", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -46,7 +47,8 @@ class PlanInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_longlong), ("spread_mode", ctypes.c_int),
                 ("spread_block", ctypes.c_int), ("spread_item", ctypes.c_int),
                 ("gather_available", ctypes.c_int), ("bins_available", ctypes.c_int),
-                ("eps", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("split", ctypes.c_int), ("split_a", ctypes.c_double),
+                ("split_P2", ctypes.c_double)]
 
 
 class Phys(ctypes.Structure):
@@ -145,10 +147,11 @@ def _ptr(t):
 
 class Plan:
     """A potential plan (nlf_plan_create).  kernel: COULOMB3D / COULOMB2D / LAPLACE2D /
-    CONFINED2D (which needs eps > 0)."""
+    CONFINED2D (which needs eps > 0).  split=True (COULOMB3D): the split evaluation of Eq. '3.9'
+    with partition width split_a (0: default)."""
 
     def __init__(self, n, L, kernel, prec=F64, n_r=0, n_theta=0, n_phi=0, P=0.0, sigma=0.0,
-                 msp=0, batch=1, stream=None, eps=0.0):
+                 msp=0, batch=1, stream=None, eps=0.0, split=False, split_a=0.0):
         import torch
         lib = load()
         self.torch = torch
@@ -157,7 +160,7 @@ class Plan:
         for i in range(len(n)):
             box.n[i] = int(n[i])
             box.L[i] = float(L[i])
-        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch, eps)
+        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch, eps, 1 if split else 0, split_a)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
