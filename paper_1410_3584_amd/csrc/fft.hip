@@ -155,6 +155,8 @@ struct RowsArgs {
     const void* tw;
     double post;           // output scale (STORE_U)
     int accum;             // STORE_U: add to u instead of overwriting it
+    int band;              // > 0: only the cells |f| < band of a line are nonzero / needed (the
+                           // ball of a split): LOAD_GRID reads only those, STORE_GRID writes only those
     // 2D Laplace: u += m0 u11 - m1 . u12 (Sec. 2.2, Eqs. 'phi1_exct', 'phi12_ext')
     int add_u1;
     const double* mom;     // [batch][4]: m0, m1x, m1y
@@ -249,7 +251,7 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
             double fac;
             int j0, j1;
             long long gl = grid_line(l, &fac, &j0, &j1);
-            buf[l * pitch + c] = grid[gl * n + c];
+            buf[l * pitch + c] = (!a.band || is_data_row(c, 2 * a.band, n)) ? grid[gl * n + c] : mk<T>(0, 0);
         }
     }
     __syncthreads();
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
             double fac;
             int j0, j1;
             long long gl = grid_line(l, &fac, &j0, &j1);
-            grid[gl * n + c] = buf[l * pitch + c];
+            if (!a.band || is_data_row(c, 2 * a.band, n)) grid[gl * n + c] = buf[l * pitch + c];
         }
     } else {
         TIO* u = reinterpret_cast<TIO*>(a.u) + (long long)b * a.rstride;
@@ -305,6 +307,10 @@ struct ColsArgs {
     int outer_mapped;       // 1: outer index o is a data index of the previous axis (pruned)
     int outer_nd, outer_Mr;
     int nd;                 // data count along this axis (for pruning)
+    int nd_store;           // > 0: SPRUNE keeps rows |f| < nd_store / 2 instead of nd
+    // > 0: only the columns of a band are transformed (the ball of a split): c2 with |f2| < bc2 of
+    // the innermost axis (length Mr2), and, for the axis-0 pass, c1 with |f1| < bc1 (length Mr1)
+    int bc1, bc2, Mr1, Mr2;
     const void* tw;
     // optional: workgroup (0, 0, b) reduces the moment partials of the row pass for field b
     const double* mom_part;
@@ -312,6 +318,19 @@ struct ColsArgs {
     double mom_w;           // cell volume
     double* mom;            // [batch][4]: m0, m1x, m1y, 0
 };
+
+// first column of column block cb: consecutive blocks of C columns, or, with a band, the blocks of
+// the band's columns (c2 in [0, bc2) and [Mr2 - bc2, Mr2); for the axis-0 pass also c1 likewise)
+__device__ __forceinline__ long long band_col(const ColsArgs& a, int cb) {
+    if (!a.bc2) return (long long)cb * a.C;
+    const int nb2 = 2 * a.bc2 / a.C;
+    const int i1 = cb / nb2, j = cb - i1 * nb2;
+    int c2 = j * a.C;
+    c2 = c2 < a.bc2 ? c2 : a.Mr2 - 2 * a.bc2 + c2;
+    if (!a.bc1) return c2;
+    const int c1 = i1 < a.bc1 ? i1 : a.Mr1 - 2 * a.bc1 + i1;
+    return (long long)c1 * a.Mr2 + c2;
+}
 
 template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E>
 __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
@@ -342,7 +361,7 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     int o = blockIdx.y;
     long long go = a.outer_mapped ? dmap(o, a.outer_nd, a.outer_Mr) : o;
     V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride +
-                  go * (long long)n * a.inner + (long long)cb * C;
+                  go * (long long)n * a.inner + band_col(a, cb);
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
         V2<T> v = mk<T>(0, 0);
@@ -351,9 +370,62 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     }
     __syncthreads();
     lds_fft<T, DIR, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    const int nds = a.nd_store > 0 ? a.nd_store : a.nd;
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
-        if (!SPRUNE || is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
+        if (!SPRUNE || is_data_row(r, nds, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
+    }
+}
+
+// Fused axis-0 pass of a split's I1 (Eq. '3.9'): per column (c1, c2) of the padded spectrum (axes
+// 1 and 2 already transformed), the forward FFT of the n0 data rows, the multiply by
+// w(k) = (1 - e^{-|k|^2/a}) / |k|^2 (w(0) = 1/a), the inverse FFT, and the store of the n0 data rows
+// only: the full Mr0-row spectrum never goes to memory.
+struct ConvW {
+    int Mr0, Mr1, Mr2;
+    double dk0, dk1, dk2, inva;
+};
+
+template <typename T, int NT, int E>
+__global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    const int n = a.n, C = a.C;
+    const int pitch = n + 1;
+    int cb = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) cb = (cb & 7) * (nb >> 3) + (cb >> 3);
+    const long long col0 = (long long)cb * C;
+    V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride + col0;
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
+        int r = idx / C, c = idx - r * C;
+        V2<T> v = mk<T>(0, 0);
+        if (is_data_row(r, a.nd, n)) v = base[(long long)r * a.inner + c];
+        buf[c * pitch + r] = v;
+    }
+    __syncthreads();
+    lds_fft<T, -1, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
+        int r = idx / C, c = idx - r * C;
+        const long long col = col0 + c;
+        const int c1 = (int)(col / cw.Mr2), c2 = (int)(col - (long long)c1 * cw.Mr2);
+        const double k0 = (r < cw.Mr0 / 2 ? r : r - cw.Mr0) * cw.dk0;
+        const double k1 = (c1 < cw.Mr1 / 2 ? c1 : c1 - cw.Mr1) * cw.dk1;
+        const double k2 = (c2 < cw.Mr2 / 2 ? c2 : c2 - cw.Mr2) * cw.dk2;
+        const double kk = k0 * k0 + k1 * k1 + k2 * k2;
+        const double w = kk > 0.0 ? -expm1(-kk * cw.inva) / kk : cw.inva;
+        V2<T> v = buf[c * pitch + r];
+        v.x = (T)((double)v.x * w);
+        v.y = (T)((double)v.y * w);
+        buf[c * pitch + r] = v;
+    }
+    __syncthreads();
+    lds_fft<T, 1, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
+        int r = idx / C, c = idx - r * C;
+        if (is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
     }
 }
 
@@ -422,7 +494,9 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     while (C > 1 && (C * (a.n + 1) > E || a.inner % C)) C >>= 1;
     if (a.n + 1 > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
     a.C = C;
-    a.ncb = (int)(a.inner / C);
+    if (a.bc2 && (a.bc2 % C || 2 * a.bc2 > (a.bc1 ? a.Mr2 : a.inner) || (a.bc1 && 2 * a.bc1 > a.Mr1)))
+        return set_error(NLF_EINVAL, "column band %d/%d does not fit the grid", a.bc1, a.bc2);
+    a.ncb = a.bc2 ? (a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / C) : (int)(a.inner / C);
     dim3 grid(a.ncb, outer, batch);
     size_t lds = (size_t)C * (a.n + 1) * sizeof(V2<T>);
     static bool attr_set = false;
@@ -443,6 +517,75 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
     return launch_cols_cfg<T, DIR, LP, SP, FftCfg<T>::NT, FftCfg<T>::E>(p, a, outer, batch);
 }
 
+template <typename T, int NT, int E>
+static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
+    a.lg = ilog2(a.n);
+    int C = 16;
+    while (C > 1 && (C * (a.n + 1) > E || a.inner % C)) C >>= 1;
+    if (a.n + 1 > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
+    a.C = C;
+    a.ncb = (int)(a.inner / C);
+    dim3 grid(a.ncb, 1, batch);
+    size_t lds = (size_t)C * (a.n + 1) * sizeof(V2<T>);
+    static bool attr_set = false;
+    if (!attr_set) {
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0<T, NT, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    E * (int)sizeof(V2<T>)));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fft_conv0<T, NT, E>), grid, dim3(NT), lds, p->stream, a, cw);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+// I1 of a split (Eq. '3.9'), 3D: the cyclic convolution of the zero-padded density with the lattice
+// transform of w, u += (1/G) IFFT(w . FFT(pad rho)), truncated to the data grid.  The plan's pre-
+// and post-correction tables are ones, so the row and axis-1 passes are the plain padded FFT; the
+// axis-0 passes and the multiply are one fused kernel.
+template <typename T>
+static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
+    RowsArgs r{};
+    r.grid = p->grid_a;
+    r.gstride = p->G;
+    r.rho = rho;
+    r.rstride = p->N;
+    r.n = p->Mr[2];
+    r.dim = 3;
+    for (int i = 0; i < 3; ++i) { r.nd[i] = p->n[i]; r.Mr[i] = p->Mr[i]; }
+    r.dec0 = p->dec[0];
+    r.dec1 = p->dec[1];
+    r.dec2 = p->dec[2];
+    r.tw = p->tw_big[2];
+    r.nlines = p->n[0] * p->n[1];
+    NLF_TRY((launch_rows<T, -1, LOAD_RHO, STORE_GRID>(p, r, p->batch)));
+    ColsArgs c{};
+    c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
+    c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
+    c.nd = p->n[1]; c.tw = p->tw_big[1];
+    NLF_TRY((launch_cols<T, -1, true, false>(p, c, p->n[0], p->batch)));
+    ColsArgs c0{};
+    c0.grid = p->grid_a; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
+    c0.nd = p->n[0]; c0.tw = p->tw_big[0];
+    ConvW cw{p->Mr[0], p->Mr[1], p->Mr[2], 0, 0, 0, 1.0 / p->split_a};
+    cw.dk0 = 2.0 * 3.14159265358979323846 / (p->Mr[0] * p->h[0]);
+    cw.dk1 = 2.0 * 3.14159265358979323846 / (p->Mr[1] * p->h[1]);
+    cw.dk2 = 2.0 * 3.14159265358979323846 / (p->Mr[2] * p->h[2]);
+    if (c0.n <= 512) NLF_TRY((launch_conv0_cfg<T, ColSmallCfg::NT, ColSmallCfg::E>(p, c0, cw, p->batch)));
+    else NLF_TRY((launch_conv0_cfg<T, FftCfg<T>::NT, FftCfg<T>::E>(p, c0, cw, p->batch)));
+    c.nd = p->n[1];
+    NLF_TRY((launch_cols<T, 1, false, true>(p, c, p->n[0], p->batch)));
+    RowsArgs ri = r;
+    ri.rho = nullptr;
+    ri.u = u;
+    ri.post = p->post;
+    ri.accum = 1;
+    return launch_rows<T, 1, LOAD_GRID, STORE_U, T>(p, ri, p->batch);
+}
+
+int fft_split_i1(nlf_plan* p, const void* rho, void* u) {
+    return p->prec == NLF_F64 ? split_i1_t<double>(p, rho, u) : split_i1_t<float>(p, rho, u);
+}
+
 template <typename T>
 static int type2_forward_t(nlf_plan* p, const void* rho) {
     const int d = p->dim;
@@ -459,6 +602,7 @@ static int type2_forward_t(nlf_plan* p, const void* rho) {
     r.dec2 = p->dec[2];
     r.tw = p->tw_big[d - 1];
     r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
+    r.band = p->band;
     // 2D Laplace: the moments m0, m1 of rho (Alg. 1) ride along the row pass
     const bool mom = (p->kernel == NLF_LAPLACE2D);
     if (mom) {
@@ -478,6 +622,19 @@ static int type2_forward_t(nlf_plan* p, const void* rho) {
             c.mom = p->mom;
         }
         NLF_TRY((launch_cols<T, -1, true, false>(p, c, 1, p->batch)));
+    } else if (p->band) {
+        // the ball of a split: only the band |f_i| < band of the spectrum is interpolated
+        ColsArgs c{};
+        c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
+        c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
+        c.nd = p->n[1]; c.nd_store = 2 * p->band; c.tw = p->tw_big[1];
+        c.bc2 = p->band; c.Mr2 = p->Mr[2];
+        NLF_TRY((launch_cols<T, -1, true, true>(p, c, p->n[0], p->batch)));
+        ColsArgs c0{};
+        c0.grid = p->grid_a; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
+        c0.nd = p->n[0]; c0.nd_store = 2 * p->band; c0.tw = p->tw_big[0];
+        c0.bc1 = p->band; c0.bc2 = p->band; c0.Mr1 = p->Mr[1]; c0.Mr2 = p->Mr[2];
+        NLF_TRY((launch_cols<T, -1, true, true>(p, c0, 1, p->batch)));
     } else {
         ColsArgs c{};
         c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
@@ -500,6 +657,19 @@ static int type1_inverse_t(nlf_plan* p, void* u, bool add_u1) {
         c.grid = p->grid_b; c.gstride = p->G; c.n = p->Mr[0]; c.inner = p->Mr[1];
         c.nd = p->n[0]; c.tw = p->tw_t1[0];
         NLF_TRY((launch_cols<T, 1, false, true>(p, c, 1, p->batch)));
+    } else if (p->band) {
+        // the ball of a split: the spreading grid is zero outside the band |f_i| < band
+        ColsArgs c0{};
+        c0.grid = p->grid_b; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
+        c0.nd = 2 * p->band; c0.nd_store = p->n[0]; c0.tw = p->tw_t1[0];
+        c0.bc1 = p->band; c0.bc2 = p->band; c0.Mr1 = p->Mr[1]; c0.Mr2 = p->Mr[2];
+        NLF_TRY((launch_cols<T, 1, true, true>(p, c0, 1, p->batch)));
+        ColsArgs c{};
+        c.grid = p->grid_b; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
+        c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
+        c.nd = 2 * p->band; c.nd_store = p->n[1]; c.tw = p->tw_t1[1];
+        c.bc2 = p->band; c.Mr2 = p->Mr[2];
+        NLF_TRY((launch_cols<T, 1, true, true>(p, c, p->n[0], p->batch)));
     } else {
         ColsArgs c0{};
         c0.grid = p->grid_b; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
@@ -524,7 +694,7 @@ static int type1_inverse_t(nlf_plan* p, void* u, bool add_u1) {
     r.dec2 = p->dec[2];
     r.tw = p->tw_t1[d - 1];
     r.post = p->post;
-    r.accum = p->split;   // a split's I1 adds to the I2 already in u
+    r.band = p->band;
     r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
     r.add_u1 = add_u1 ? 1 : 0;
     r.mom = p->mom;

@@ -75,6 +75,8 @@ struct nlf_plan {
     double split_a = 0.0, split_P2 = 0.0;
     nlf_plan* sub = nullptr;
     double pweight_a = 0.0;     // ball plan of a split: node weights times exp(-|k|^2 / a)
+    int band = 0;               // ball plan of a split: spectrum cells |f_i| < band (3D) hold every
+                                // value the interpolation reads and the spreading writes
     int n_r, n_theta, n_phi;
     long long N, G, M, Mh;      // grid points, oversampled grid points, nodes, half nodes
     hipStream_t stream;
@@ -157,6 +159,7 @@ size_t elem_size(int prec);  // bytes of one complex element in the plan precisi
 // FFT front-ends (fft.hip)
 int fft_type2_forward(nlf_plan* p, const void* rho);          // rho -> grid_a (pruned, fused precorrect)
 int fft_type1_inverse(nlf_plan* p, void* u, bool add_u1);     // grid_b -> u (pruned, fused postcorrect)
+int fft_split_i1(nlf_plan* p, const void* rho, void* u);      // u += I1 of a split (Eq. '3.9')
 int fft_full(nlf_plan* p, void* data, int dir, int batch);    // n-grid complex FFT in place, all axes
 int fill_zero(nlf_plan* p, void* ptr, size_t bytes);
 int set_items(nlf_plan* p, int cap, bool bins);               // rebuild the gather work items

@@ -1050,39 +1050,32 @@ int fold_c(nlf_plan* p, const void* c) {
         NLF_TRY(stage_end(p, id, mk_));      \
     } while (0)
 
-// I1 of the split evaluation: the padded spectrum times w(k) = (1 - e^{-|k|^2/a}) / |k|^2, w(0) = 1/a,
-// at the lattice frequency of each cell (index c -> c or c - Mr, times dk = 2 pi / (Mr h)), in place.
+// the band cube |f_i| < band of the spreading grid of a split's ball (the only cells spread into)
 template <typename T>
-__global__ void k_split_w(V2<T>* __restrict__ grid, long long G, int Mr0, int Mr1, int Mr2, double dk0, double dk1,
-                          double dk2, double inva) {
+__global__ void k_zero_band(V2<T>* __restrict__ grid, long long G, int band, int Mr1, int Mr2, int Mr0) {
     V2<T>* g = grid + (long long)blockIdx.y * G;
-    const long long plane = (long long)Mr1 * Mr2;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < G; i += (long long)gridDim.x * blockDim.x) {
-        const int c0 = (int)(i / plane);
-        const int r = (int)(i - c0 * plane);
-        const int c1 = r / Mr2, c2 = r - c1 * Mr2;
-        const double k0 = (c0 < Mr0 / 2 ? c0 : c0 - Mr0) * dk0;
-        const double k1 = (c1 < Mr1 / 2 ? c1 : c1 - Mr1) * dk1;
-        const double k2 = (c2 < Mr2 / 2 ? c2 : c2 - Mr2) * dk2;
-        const double kk = k0 * k0 + k1 * k1 + k2 * k2;
-        const double w = kk > 0.0 ? -expm1(-kk * inva) / kk : inva;
-        V2<T> v = g[i];
-        v.x = (T)((double)v.x * w);
-        v.y = (T)((double)v.y * w);
-        g[i] = v;
+    const int w = 2 * band;
+    const long long cnt = (long long)w * w * w;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (long long)gridDim.x * blockDim.x) {
+        const int i0 = (int)(i / ((long long)w * w)), r = (int)(i - (long long)i0 * w * w);
+        const int i1 = r / w, i2 = r - i1 * w;
+        const int c0 = i0 < band ? i0 : Mr0 - w + i0;
+        const int c1 = i1 < band ? i1 : Mr1 - w + i1;
+        const int c2 = i2 < band ? i2 : Mr2 - w + i2;
+        g[((long long)c0 * Mr1 + c1) * Mr2 + c2] = mk2<T>((T)0, (T)0);
     }
 }
 
-static int split_w(nlf_plan* p) {
-    double dk[3];
-    for (int i = 0; i < 3; ++i) dk[i] = 2.0 * 3.14159265358979323846 / (p->Mr[i] * p->h[i]);
-    dim3 grid((unsigned)std::min<long long>((p->G + 255) / 256, 16384), p->batch);
-    if (p->prec == NLF_F64)
-        hipLaunchKernelGGL((k_split_w<double>), grid, dim3(256), 0, p->stream, (double2*)p->grid_a, p->G, p->Mr[0],
-                           p->Mr[1], p->Mr[2], dk[0], dk[1], dk[2], 1.0 / p->split_a);
+static int zero_spread_grid(nlf_plan* p) {
+    if (!p->band) return fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec));
+    const long long w = 2LL * p->band;
+    dim3 grid((unsigned)std::min<long long>((w * w * w + 255) / 256, 8192), p->batch);
+    if (p->t1_prec == NLF_F64)
+        hipLaunchKernelGGL((k_zero_band<double>), grid, dim3(256), 0, p->stream, (double2*)p->grid_b, p->G, p->band,
+                           p->Mr[1], p->Mr[2], p->Mr[0]);
     else
-        hipLaunchKernelGGL((k_split_w<float>), grid, dim3(256), 0, p->stream, (float2*)p->grid_a, p->G, p->Mr[0],
-                           p->Mr[1], p->Mr[2], dk[0], dk[1], dk[2], 1.0 / p->split_a);
+        hipLaunchKernelGGL((k_zero_band<float>), grid, dim3(256), 0, p->stream, (float2*)p->grid_b, p->G, p->band,
+                           p->Mr[1], p->Mr[2], p->Mr[0]);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -1093,9 +1086,7 @@ int potential(nlf_plan* p, const void* rho, void* u) {
         // padded density with w adds to it; the ball plan follows this plan's current stream
         p->sub->stream = p->stream;
         NLF_TRY(potential(p->sub, rho, u));
-        NLF_STAGE(p, NLF_STAGE_FFT_FWD, fft_type2_forward(p, rho));
-        NLF_STAGE(p, NLF_STAGE_FFT_INV, split_w(p));
-        NLF_STAGE(p, NLF_STAGE_FFT_INV, fft_type1_inverse(p, u, false));
+        NLF_STAGE(p, NLF_STAGE_FFT_INV, fft_split_i1(p, rho, u));
         return NLF_OK;
     }
     const bool lap = p->kernel == NLF_LAPLACE2D;   // moments m0, m1: computed by the forward FFT
@@ -1103,8 +1094,7 @@ int potential(nlf_plan* p, const void* rho, void* u) {
     // 2D: the interpolation kernel also clears the spreading grid (the zero stage then reports 0)
     const bool fused_zero = (p->dim == 2);
     NLF_STAGE(p, NLF_STAGE_INTERP, interp(p, 0, nullptr, fused_zero));
-    if (!fused_zero)
-        NLF_STAGE(p, NLF_STAGE_ZERO, fill_zero(p, p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
+    if (!fused_zero) NLF_STAGE(p, NLF_STAGE_ZERO, zero_spread_grid(p));
     NLF_STAGE(p, NLF_STAGE_SPREAD, spread_only(p));
     NLF_STAGE(p, NLF_STAGE_FFT_INV, fft_type1_inverse(p, u, lap));
     return NLF_OK;

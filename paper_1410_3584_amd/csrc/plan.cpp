@@ -207,6 +207,21 @@ static int build_split(nlf_plan* p, const nlf_box* box, int kernel, const nlf_op
     so.n_theta = o->n_theta > 0 ? o->n_theta : nr;
     so.n_phi = o->n_phi > 0 ? o->n_phi : 2 * nr;
     NLF_TRY(plan_create(box, kernel, &so, p->stream, p->split_a, &p->sub));
+    // the ball's spectrum band: node positions reach 2 L_i P2 / pi oversampled cells from the
+    // origin, stencils msp more and whole gather tiles (<= 8 cells) one more; rounded up to whole
+    // 16-column blocks.  Cells outside it are never read or written by the ball's FFT passes.
+    {
+        nlf_plan* b = p->sub;
+        double reach = 0;
+        for (int i = 0; i < 3; ++i) reach = std::max(reach, 2.0 * p->L[i] * p->split_P2 / 3.14159265358979323846);
+        int band = ((int)std::ceil(reach) + b->msp + 9 + 15) / 16 * 16;
+        bool fits = true;
+        for (int i = 0; i < 3; ++i) fits = fits && 2 * band <= b->Mr[i] / 2;
+        if (fits) {
+            b->band = band;
+            NLF_HIP(hipMemset(b->grid_a, 0, (size_t)b->batch * b->G * elem_size(b->prec)));
+        }
+    }
     p->n_r = p->sub->n_r;
     p->n_theta = p->sub->n_theta;
     p->n_phi = p->sub->n_phi;
