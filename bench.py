@@ -186,8 +186,48 @@ def ground_states_per_s(torch, nlf, inputs):
             "mean_outer_iters": float(np.mean([s["iters"] for s in flat])),
             "mean_fp32_iters": float(np.mean([s["iters_fp32"] for s in flat])),
             "sizes": {str(k): len(groups[k]) for k in keys},
-            "spread_autotuned": {k: {"mode": "gather" if v[0] == 0 else "scatter", "block": v[1], "item": v[2]}
+            "spread_autotuned": {k: {"mode": ("gather", "scatter", "bins")[v[0]], "block": v[1], "item": v[2]}
                                  for k, v in tuned.items()}}
+
+
+def dynamics_3d(torch, nlf, inputs, steps=20):
+    """Third workload: 3D Coulomb-cubic time splitting on 256^3 of [-12,12]^3, harmonic trap,
+    normalised Gaussian with seeded phase modulation, beta = 50, dt = 1e-3, Strang steps, FP64,
+    with the split evaluation of the potential (Eq. '3.9'); one potential of the plain ball
+    evaluation is timed beside it.  Reports steps/s over `steps` timed steps after 2 untimed
+    ones, and the mass/energy drift over them."""
+    n, L = (256,) * 3, (12.0,) * 3
+    psi0 = inputs.psi0_phase_modulated(n, L, seed=0)
+    psi = torch.tensor(psi0, dtype=torch.complex128, device="cuda")
+    rho = (psi.abs() ** 2).contiguous()
+    out = {"workload": "3D dynamics, 256^3 on [-12,12]^3, Coulomb, beta 50, dt 1e-3, Strang, FP64"}
+    ball = nlf.Plan(n, L, nlf.COULOMB3D)
+    ball.potential(rho)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ball.potential(rho)
+    torch.cuda.synchronize()
+    out["ball_potential_ms"] = 1e3 * (time.perf_counter() - t0)
+    del ball
+    torch.cuda.empty_cache()
+    plan = nlf.Plan(n, L, nlf.COULOMB3D, split=True)
+    u = plan.potential(rho)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        plan.potential(rho, u)
+    torch.cuda.synchronize()
+    out["split_potential_ms"] = 1e3 * (time.perf_counter() - t0) / 5
+    plan.evolve(psi, 50.0, (1.0, 1.0, 1.0), 1e-3, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diag = plan.evolve(psi, 50.0, (1.0, 1.0, 1.0), 1e-3, steps, diag_every=steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out.update({"steps": steps, "steps_per_s": steps / dt,
+                "mass_drift": float(abs(diag[-1, 0, 0] - diag[0, 0, 0])),
+                "energy_rel_drift": float(abs(diag[-1, 0, 1] - diag[0, 0, 1]) / abs(diag[0, 0, 1]))})
+    return out
 
 
 def main():
@@ -195,9 +235,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["full", "prof"], default="full")
+    ap.add_argument("--mode", choices=["full", "prof", "prof3d"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ground-states", action="store_true")
+    ap.add_argument("--no-dynamics-3d", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -210,6 +251,19 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.mode == "prof3d":
+        # the 3D dynamics workload's split potential evaluations and steps, for a kernel trace
+        n3, L3 = (256,) * 3, (12.0,) * 3
+        psi = torch.tensor(inputs.psi0_phase_modulated(n3, L3, seed=0), dtype=torch.complex128, device="cuda")
+        rho3 = (psi.abs() ** 2).contiguous()
+        plan = nlf.Plan(n3, L3, nlf.COULOMB3D, split=True)
+        u = plan.potential(rho3)
+        for _ in range(max(1, args.steps)):
+            plan.potential(rho3, u)
+        plan.evolve(psi, 50.0, (1.0, 1.0, 1.0), 1e-3, max(1, args.steps))
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "prof3d", "steps": args.steps}))
+        return
     n, L, rho, _ = inputs.potential_2d_512(seed=1)
     dev = "cuda"
     r64 = torch.tensor(rho, dtype=torch.float64, device=dev)
@@ -299,6 +353,7 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(n, L, rho)
     gs = None if args.no_ground_states else ground_states_per_s(torch, nlf, inputs)
+    dyn = None if args.no_dynamics_3d else dynamics_3d(torch, nlf, inputs)
 
     value = 2 * args.steps / t64
     out = {
@@ -323,6 +378,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "ground_states": gs,
+        "dynamics_3d": dyn,
     }
     print(json.dumps(out))
 

@@ -50,89 +50,120 @@ __device__ __forceinline__ bool is_data_row(int r, int nd, int Mr) { return r < 
 
 // In-place multi-line Stockham FFT of nl lines of length n = 2^lg held in buf[line*pitch + i].
 // tw[t] = exp(-2 pi i t / n).  DIR = -1 forward, +1 inverse (unnormalised).
+// Mixed radix: one radix-2 or radix-4 pass first when lg is not a multiple of 3, then radix-8
+// passes, each a read of the whole buffer into registers and a write back (fewer LDS round trips
+// than radix 4: 512 points take 3 passes instead of 5).  Pass with radix R over the index range
+// q = n / R, after p = product of the earlier radices: butterfly i (k = i mod p) reads
+// x[i + m q], m < R, scales element m by w^(m k n / (R p)), takes the length-R DFT and writes
+// element m to x[(i - k) R + k + m p].
+template <typename T, int DIR>
+__device__ __forceinline__ void dft4(V2<T>& a0, V2<T>& a1, V2<T>& a2, V2<T>& a3) {
+    const V2<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2), t2 = cadd<T>(a1, a3), t3 = csub<T>(a1, a3);
+    a0 = cadd<T>(t0, t2);
+    a2 = csub<T>(t0, t2);
+    if (DIR < 0) {
+        a1 = mk<T>(t1.x + t3.y, t1.y - t3.x);
+        a3 = mk<T>(t1.x - t3.y, t1.y + t3.x);
+    } else {
+        a1 = mk<T>(t1.x - t3.y, t1.y + t3.x);
+        a3 = mk<T>(t1.x + t3.y, t1.y - t3.x);
+    }
+}
+
+// length-8 DFT in place: even and odd halves by dft4, combined with w8^k = exp(DIR 2 pi i k / 8)
+template <typename T, int DIR>
+__device__ __forceinline__ void dft8(V2<T> (&a)[8]) {
+    dft4<T, DIR>(a[0], a[2], a[4], a[6]);
+    dft4<T, DIR>(a[1], a[3], a[5], a[7]);
+    const T h = (T)0.70710678118654752440;
+    // odd part times w8^k, k = 0..3 (a[1], a[3], a[5], a[7] hold O_0..O_3)
+    V2<T> o1 = a[3], o2 = a[5], o3 = a[7];
+    if (DIR < 0) {
+        o1 = mk<T>(h * (o1.x + o1.y), h * (o1.y - o1.x));     // (1 - i)/sqrt2
+        o2 = mk<T>(o2.y, -o2.x);                               // -i
+        o3 = mk<T>(h * (o3.y - o3.x), -h * (o3.x + o3.y));    // (-1 - i)/sqrt2
+    } else {
+        o1 = mk<T>(h * (o1.x - o1.y), h * (o1.y + o1.x));     // (1 + i)/sqrt2
+        o2 = mk<T>(-o2.y, o2.x);                               // i
+        o3 = mk<T>(-h * (o3.x + o3.y), h * (o3.x - o3.y));    // (-1 + i)/sqrt2
+    }
+    const V2<T> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6], o0 = a[1];
+    a[0] = cadd<T>(e0, o0);
+    a[4] = csub<T>(e0, o0);
+    a[1] = cadd<T>(e1, o1);
+    a[5] = csub<T>(e1, o1);
+    a[2] = cadd<T>(e2, o2);
+    a[6] = csub<T>(e2, o2);
+    a[3] = cadd<T>(e3, o3);
+    a[7] = csub<T>(e3, o3);
+}
+
+template <typename T, int DIR, int NT, int E, int R>
+__device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, int p, const V2<T>* __restrict__ tw) {
+    constexpr int RB = (E + R * NT - 1) / (R * NT);   // butterflies per thread
+    const int q = n / R;
+    const int tot = nl * q;
+    const int tstep = n / (R * p);
+    const int tid = threadIdx.x;
+    V2<T> y[RB][R];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int idx = tid + r * NT;
+        if (idx < tot) {
+            const int line = idx / q, i = idx - line * q;
+            const int k = i & (p - 1);
+            const V2<T>* x = buf + line * pitch;
+#pragma unroll
+            for (int m = 0; m < R; ++m) y[r][m] = x[i + m * q];
+            if (p > 1) {
+#pragma unroll
+                for (int m = 1; m < R; ++m) {
+                    V2<T> w = tw[m * k * tstep];
+                    if (DIR > 0) w.y = -w.y;
+                    y[r][m] = cmul<T>(y[r][m], w);
+                }
+            }
+            if constexpr (R == 2) {
+                const V2<T> a0 = y[r][0], a1 = y[r][1];
+                y[r][0] = cadd<T>(a0, a1);
+                y[r][1] = csub<T>(a0, a1);
+            } else if constexpr (R == 4) {
+                dft4<T, DIR>(y[r][0], y[r][1], y[r][2], y[r][3]);
+            } else {
+                static_assert(R == 8, "radix 2, 4 or 8");
+                dft8<T, DIR>(y[r]);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int idx = tid + r * NT;
+        if (idx < tot) {
+            const int line = idx / q, i = idx - line * q;
+            const int k = i & (p - 1);
+            const int j = (i - k) * R + k;
+            V2<T>* x = buf + line * pitch;
+#pragma unroll
+            for (int m = 0; m < R; ++m) x[j + m * p] = y[r][m];
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int DIR, int NT, int E>
 __device__ void lds_fft(V2<T>* buf, int pitch, int n, int lg, int nl, const V2<T>* __restrict__ tw) {
-    constexpr int RB = E / (4 * NT);   // radix-4 butterflies per thread
-    const int tid = threadIdx.x;
     int p = 1;
-    if (lg & 1) {
-        const int h = n >> 1;
-        const int tot = nl * h;
-        V2<T> y0[2 * RB], y1[2 * RB];
-#pragma unroll
-        for (int r = 0; r < 2 * RB; ++r) {
-            int idx = tid + r * NT;
-            if (idx < tot) {
-                int line = idx / h, i = idx - line * h;
-                V2<T>* x = buf + line * pitch;
-                V2<T> a0 = x[i], a1 = x[i + h];
-                y0[r] = cadd<T>(a0, a1);
-                y1[r] = csub<T>(a0, a1);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 2 * RB; ++r) {
-            int idx = tid + r * NT;
-            if (idx < tot) {
-                int line = idx / h, i = idx - line * h;
-                V2<T>* x = buf + line * pitch;
-                x[2 * i] = y0[r];
-                x[2 * i + 1] = y1[r];
-            }
-        }
-        __syncthreads();
+    if (lg % 3 == 1) {
+        fft_pass<T, DIR, NT, E, 2>(buf, pitch, n, nl, p, tw);
         p = 2;
+    } else if (lg % 3 == 2) {
+        fft_pass<T, DIR, NT, E, 4>(buf, pitch, n, nl, p, tw);
+        p = 4;
     }
-    const int q = n >> 2;
-    const int tot = nl * q;
     while (p < n) {
-        V2<T> y[RB][4];
-        const int tstep = n / (4 * p);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            int idx = tid + r * NT;
-            if (idx < tot) {
-                int line = idx / q, i = idx - line * q;
-                int k = i & (p - 1);
-                V2<T>* x = buf + line * pitch;
-                V2<T> a0 = x[i], a1 = x[i + q], a2 = x[i + 2 * q], a3 = x[i + 3 * q];
-                if (p > 1) {
-                    V2<T> w1 = tw[k * tstep], w2 = tw[2 * k * tstep], w3 = tw[3 * k * tstep];
-                    if (DIR > 0) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
-                    a1 = cmul<T>(a1, w1);
-                    a2 = cmul<T>(a2, w2);
-                    a3 = cmul<T>(a3, w3);
-                }
-                V2<T> t0 = cadd<T>(a0, a2), t1 = csub<T>(a0, a2), t2 = cadd<T>(a1, a3), t3 = csub<T>(a1, a3);
-                y[r][0] = cadd<T>(t0, t2);
-                y[r][2] = csub<T>(t0, t2);
-                if (DIR < 0) {
-                    y[r][1] = mk<T>(t1.x + t3.y, t1.y - t3.x);
-                    y[r][3] = mk<T>(t1.x - t3.y, t1.y + t3.x);
-                } else {
-                    y[r][1] = mk<T>(t1.x - t3.y, t1.y + t3.x);
-                    y[r][3] = mk<T>(t1.x + t3.y, t1.y - t3.x);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            int idx = tid + r * NT;
-            if (idx < tot) {
-                int line = idx / q, i = idx - line * q;
-                int k = i & (p - 1);
-                int j = (i - k) * 4 + k;
-                V2<T>* x = buf + line * pitch;
-                x[j] = y[r][0];
-                x[j + p] = y[r][1];
-                x[j + 2 * p] = y[r][2];
-                x[j + 3 * p] = y[r][3];
-            }
-        }
-        __syncthreads();
-        p *= 4;
+        fft_pass<T, DIR, NT, E, 8>(buf, pitch, n, nl, p, tw);
+        p *= 8;
     }
 }
 
@@ -490,8 +521,14 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
 template <typename T, int DIR, bool LP, bool SP, int NT, int E>
 static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     a.lg = ilog2(a.n);
+    // C adjacent columns per workgroup: as many as the element budget E allows (the padded pitch
+    // n + 1 adds at most C <= 16 elements of LDS), wider row segments coalesce better, but not so
+    // many that fewer than 256 workgroups remain (one per CU)
+    auto blocks = [&](int c) -> long long {
+        return (a.bc2 ? (long long)(a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / c) : a.inner / c) * outer * batch;
+    };
     int C = 16;
-    while (C > 1 && (C * (a.n + 1) > E || a.inner % C)) C >>= 1;
+    while (C > 1 && (C * a.n > E || a.inner % C || blocks(C) < 256)) C >>= 1;
     if (a.n + 1 > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
     a.C = C;
     if (a.bc2 && (a.bc2 % C || 2 * a.bc2 > (a.bc1 ? a.Mr2 : a.inner) || (a.bc1 && 2 * a.bc1 > a.Mr1)))
@@ -502,7 +539,7 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     static bool attr_set = false;
     if (!attr_set) {
         NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP, NT, E>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (E + 16) * (int)sizeof(V2<T>)));
         attr_set = true;
     }
     hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP, NT, E>), grid, dim3(NT), lds, p->stream, a);
@@ -520,8 +557,8 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
 template <typename T, int NT, int E>
 static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     a.lg = ilog2(a.n);
-    int C = 16;
-    while (C > 1 && (C * (a.n + 1) > E || a.inner % C)) C >>= 1;
+    int C = 16;   // as in launch_cols_cfg
+    while (C > 1 && (C * a.n > E || a.inner % C || (a.inner / C) * batch < 256)) C >>= 1;
     if (a.n + 1 > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
     a.C = C;
     a.ncb = (int)(a.inner / C);
@@ -530,7 +567,7 @@ static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     static bool attr_set = false;
     if (!attr_set) {
         NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0<T, NT, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    E * (int)sizeof(V2<T>)));
+                                    (E + 16) * (int)sizeof(V2<T>)));
         attr_set = true;
     }
     hipLaunchKernelGGL((k_fft_conv0<T, NT, E>), grid, dim3(NT), lds, p->stream, a, cw);
