@@ -93,3 +93,50 @@ def test_split_argument_checks():
         nlf.Plan((64, 64), (8.0, 8.0), nlf.COULOMB2D, split=True)
     with pytest.raises(nlf.NlfError):          # the cube is the grid's; no P
         nlf.Plan((32,) * 3, (8.0,) * 3, nlf.COULOMB3D, split=True, P=3.0)
+
+
+def test_split_batched_fields_and_ball_stage_entries():
+    """A batch of two fields equals two single evaluations; the stage entries of a split plan act
+    on the ball's nodes (type-2 at sampled ball nodes against the oracle's direct sum; type-1 of
+    those values against the oracle's sum); the tuner runs on the ball."""
+    n, L = (32,) * 3, (8.0,) * 3
+    print("[split batch/stages]", flush=True)
+    from oracle import potential as op
+    r1 = _density(n, L)
+    r2 = np.roll(r1, 3, axis=1) * 0.5
+    pb = nlf.Plan(n, L, nlf.COULOMB3D, split=True, batch=2)
+    ub = pb.potential(to_dev(np.stack([r1, r2]), nlf.F64)).cpu().numpy()
+    ps = nlf.Plan(n, L, nlf.COULOMB3D, split=True)
+    for i, r in enumerate((r1, r2)):
+        assert rel_err(ub[i], ps.potential(to_dev(r, nlf.F64)).cpu().numpy()) < 1e-13
+    k, w = ps.nodes()
+    assert len(k) == ps.info.n_nodes and np.max(np.linalg.norm(k, axis=1)) <= ps.info.split_P2 * (1 + 1e-12)
+    rh = ps.type2(to_dev(r1, nlf.F64)).cpu().numpy()
+    sel = np.random.default_rng(1).choice(len(k), 12, replace=False)
+    want = op.type2_direct(r1, n, L, k[sel])
+    assert np.max(np.abs(rh[sel] - want)) <= 1e-10 * np.max(np.abs(rh))
+    c = (np.random.default_rng(2).normal(size=len(k)) + 0j) / len(k)
+    got = ps.type1(torch.tensor(c, dtype=torch.complex128, device="cuda")).cpu().numpy()
+    assert rel_err(got, op.type1_direct(c, n, L, k)) <= 1e-10
+    best, ms = ps.autotune(reps=1)
+    assert ms > 0
+    assert rel_err(ps.potential(to_dev(r1, nlf.F64)).cpu().numpy(), ub[0]) < 1e-12
+
+
+def test_split_mixed_schedule_and_graphs():
+    """An FP32 split plan in the mixed gradient flow (its FP64 twin is a split plan too) and an
+    FP64 split plan with graph capture reach the FP64 split plan's ground state."""
+    n, L = (64,) * 3, (6.0,) * 3
+    print("[split mixed/graphs]", flush=True)
+    ref = nlf.Plan(n, L, nlf.COULOMB3D, split=True)
+    psi_r, st_r, s0 = ref.ground_state(10.0, (1.0, 1.1, 1.2), tau=0.5, eps0=1e-10)
+    assert s0 == nlf.OK
+    p32 = nlf.Plan(n, L, nlf.COULOMB3D, split=True, prec=nlf.F32)
+    psi_m, st_m, s1 = p32.ground_state(10.0, (1.0, 1.1, 1.2), tau=0.5, eps0=1e-10, mixed=True)
+    assert s1 == nlf.OK
+    assert abs(st_m[0]["E"] - st_r[0]["E"]) < 1e-9 * abs(st_r[0]["E"])
+    pg = nlf.Plan(n, L, nlf.COULOMB3D, split=True)
+    psi_g, st_g, s2 = pg.ground_state(10.0, (1.0, 1.1, 1.2), tau=0.5, eps0=1e-10, graph=True)
+    assert s2 == nlf.OK
+    assert abs(st_g[0]["E"] - st_r[0]["E"]) < 1e-10 * abs(st_r[0]["E"])
+    assert rel_err(psi_g.cpu().numpy(), psi_r.cpu().numpy()) < 1e-9
