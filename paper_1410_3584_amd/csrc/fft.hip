@@ -35,10 +35,11 @@ template <typename T> __device__ __forceinline__ V2<T> cmul(V2<T> a, V2<T> b) {
 template <typename T> struct FftCfg;
 template <> struct FftCfg<double> { static constexpr int E = 8192, NT = 512; };
 template <> struct FftCfg<float>  { static constexpr int E = 16384, NT = 1024; };
-struct RowCfg { static constexpr int E = 2048, NT = 256; };
-// Strided-axis kernel for short columns (n <= 512): a quarter of the LDS and half the threads of
-// FftCfg, so that several workgroups share a CU.
-struct ColSmallCfg { static constexpr int E = 4096, NT = 256; };
+struct RowCfg { static constexpr int E = 2048, NT = 512; };
+// Strided-axis kernel for short columns (n <= 512): half the LDS of FftCfg, so that two workgroups
+// share a CU, and 1024 threads, so that each thread has few loads in flight (measured at 256^3:
+// 256 threads 7.3 ms per split potential, 512 threads 6.5 ms, 1024 threads 6.2 ms).
+struct ColSmallCfg { static constexpr int E = 4096, NT = 1024; };
 
 // data index j (0..nd-1, x_j = -L + j h) -> row of the 2x oversampled periodic grid holding
 // centred frequency/position j - nd/2
@@ -244,25 +245,44 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     if (LOAD == LOAD_RHO) {
         const TIO* rho = reinterpret_cast<const TIO*>(a.rho) + (long long)b * a.rstride;
         double m0 = 0.0, mx = 0.0, my = 0.0;   // moments of the rows read (2D Laplace)
-        for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
-            int l = idx / n, c = idx - l * n;
-            double fac = 1;
-            int j0 = 0, j1 = 0;
-            (void)grid_line(l, &fac, &j0, &j1);
-            // oversampled position c holds data index j with dmap(j) == c, if any
-            V2<T> v = mk<T>(0, 0);
-            if (is_data_row(c, ndl, n)) {
-                int j = (c < ndl / 2) ? c + ndl / 2 : c - (n - ndl / 2);
-                long long src = (long long)(line0 + l) * ndl + j;
-                const double rv = (double)rho[src];
-                v.x = (T)(rv * fac * decl[j]);
-                if (a.mom_part) {
-                    m0 += rv;
-                    mx += rv * (-a.L0 + (line0 + l) * a.h0);
-                    my += rv * (-a.L1 + j * a.h1);
+        // every load of the thread is issued before the first use (one memory latency, not PER)
+        constexpr int PER = (E + NT - 1) / NT;
+        double rv[PER], dv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            rv[u] = 0.0;
+            dv[u] = 0.0;
+            if (idx < nl * n) {
+                const int l = idx / n, c = idx - l * n;
+                // oversampled position c holds data index j with dmap(j) == c, if any
+                if (is_data_row(c, ndl, n)) {
+                    const int j = (c < ndl / 2) ? c + ndl / 2 : c - (n - ndl / 2);
+                    rv[u] = (double)rho[(long long)(line0 + l) * ndl + j];
+                    dv[u] = decl[j];
                 }
             }
-            buf[l * pitch + c] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            if (idx < nl * n) {
+                const int l = idx / n, c = idx - l * n;
+                double fac = 1;
+                int j0 = 0, j1 = 0;
+                (void)grid_line(l, &fac, &j0, &j1);
+                V2<T> v = mk<T>(0, 0);
+                if (is_data_row(c, ndl, n)) {
+                    const int j = (c < ndl / 2) ? c + ndl / 2 : c - (n - ndl / 2);
+                    v.x = (T)(rv[u] * fac * dv[u]);
+                    if (a.mom_part) {
+                        m0 += rv[u];
+                        mx += rv[u] * (-a.L0 + (line0 + l) * a.h0);
+                        my += rv[u] * (-a.L1 + j * a.h1);
+                    }
+                }
+                buf[l * pitch + c] = v;
+            }
         }
         if (a.mom_part) {   // uniform over the workgroup
             __shared__ double red16[16];
@@ -277,12 +297,24 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
             }
         }
     } else {
-        for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
-            int l = idx / n, c = idx - l * n;
-            double fac;
-            int j0, j1;
-            long long gl = grid_line(l, &fac, &j0, &j1);
-            buf[l * pitch + c] = (!a.band || is_data_row(c, 2 * a.band, n)) ? grid[gl * n + c] : mk<T>(0, 0);
+        constexpr int PER = (E + NT - 1) / NT;
+        V2<T> v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            v[u] = mk<T>(0, 0);
+            if (idx < nl * n) {
+                const int l = idx / n, c = idx - l * n;
+                double fac;
+                int j0, j1;
+                const long long gl = grid_line(l, &fac, &j0, &j1);
+                if (!a.band || is_data_row(c, 2 * a.band, n)) v[u] = grid[gl * n + c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * NT;
+            if (idx < nl * n) buf[(idx / n) * pitch + idx % n] = v[u];
         }
     }
     __syncthreads();
@@ -393,11 +425,22 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     long long go = a.outer_mapped ? dmap(o, a.outer_nd, a.outer_Mr) : o;
     V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride +
                   go * (long long)n * a.inner + band_col(a, cb);
-    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
-        int r = idx / C, c = idx - r * C;
-        V2<T> v = mk<T>(0, 0);
-        if (!LPRUNE || is_data_row(r, a.nd, n)) v = base[(long long)r * a.inner + c];
-        buf[c * pitch + r] = v;
+    // every load of the thread is issued before the first LDS write (one memory latency, not PER)
+    constexpr int PER = (E + NT - 1) / NT;
+    V2<T> v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        v[u] = mk<T>(0, 0);
+        if (idx < n * C) {
+            const int r = idx / C, c = idx - r * C;
+            if (!LPRUNE || is_data_row(r, a.nd, n)) v[u] = base[(long long)r * a.inner + c];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        if (idx < n * C) buf[(idx % C) * pitch + idx / C] = v[u];
     }
     __syncthreads();
     lds_fft<T, DIR, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
@@ -428,11 +471,21 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
     if ((nb & 7) == 0) cb = (cb & 7) * (nb >> 3) + (cb >> 3);
     const long long col0 = (long long)cb * C;
     V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride + col0;
-    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
-        int r = idx / C, c = idx - r * C;
-        V2<T> v = mk<T>(0, 0);
-        if (is_data_row(r, a.nd, n)) v = base[(long long)r * a.inner + c];
-        buf[c * pitch + r] = v;
+    constexpr int PER = (E + NT - 1) / NT;
+    V2<T> v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        v[u] = mk<T>(0, 0);
+        if (idx < n * C) {
+            const int r = idx / C, c = idx - r * C;
+            if (is_data_row(r, a.nd, n)) v[u] = base[(long long)r * a.inner + c];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = threadIdx.x + u * NT;
+        if (idx < n * C) buf[(idx % C) * pitch + idx / C] = v[u];
     }
     __syncthreads();
     lds_fft<T, -1, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));

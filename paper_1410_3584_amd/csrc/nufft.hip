@@ -176,11 +176,23 @@ __global__ void __launch_bounds__(kChunk) k_interp3(const V2<T>* __restrict__ gr
         r2 = wrap(l2, na.Mr[2]) - ch.t2 * na.tile[2];
     }
     double ax = 0, ay = 0;
+    // a plane's window: every load of a thread is issued before its first LDS store
+    constexpr int PER = ((8 + 2 * MSP - 1) * (8 + 2 * MSP - 1) + kChunk - 1) / kChunk;
     for (int q = 0; q < NP; ++q) {
         const V2<T>* gp = g + (long long)wrap(o0 + q, na.Mr[0]) * plane;
-        for (int idx = threadIdx.x; idx < W1 * W2; idx += kChunk) {
-            int r = idx / W2, c = idx - r * W2;
-            win[idx] = gp[(long long)wrap(o1 + r, na.Mr[1]) * na.Mr[2] + wrap(o2 + c, na.Mr[2])];
+        V2<T> pv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * kChunk;
+            if (idx < W1 * W2) {
+                const int r = idx / W2, c = idx - r * W2;
+                pv[u] = gp[(long long)wrap(o1 + r, na.Mr[1]) * na.Mr[2] + wrap(o2 + c, na.Mr[2])];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = threadIdx.x + u * kChunk;
+            if (idx < W1 * W2) win[idx] = pv[u];
         }
         __syncthreads();
         const int a = q - r0;
@@ -625,11 +637,25 @@ __global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ g
     const int o0 = ch.t0 * 8 - (MSP - 1), o1 = ch.t1 * 16 - (MSP - 1);
     // lane quads read 4 adjacent columns of one row (64-byte segments); a wave covers 16 rows, so
     // its column-major LDS stores hit each bank at most twice
-    for (int idx = t; idx < NRW * NCW; idx += 256) {
-        const int c = 4 * (idx / (4 * NRW)) + (idx & 3), r = (idx >> 2) % NRW;
-        const V2<T> v = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
-        Gp[c * PX + r] = (double)v.x;
-        Gp[PL + c * PX + r] = (double)v.y;
+    // all of a thread's window loads are issued before the first LDS store
+    constexpr int PER = (NRW * NCW + 255) / 256;
+    V2<T> gv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        if (idx < NRW * NCW) {
+            const int c = 4 * (idx / (4 * NRW)) + (idx & 3), r = (idx >> 2) % NRW;
+            gv[u] = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        if (idx < NRW * NCW) {
+            const int c = 4 * (idx / (4 * NRW)) + (idx & 3), r = (idx >> 2) % NRW;
+            Gp[c * PX + r] = (double)gv[u].x;
+            Gp[PL + c * PX + r] = (double)gv[u].y;
+        }
     }
     if (t < ch.count) {
         const int node = ch.start + t;
@@ -759,17 +785,35 @@ __global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict
             cell = ((long long)x * na.Mr[1] + o1 + (j >> 2)) * na.Mr[2] + o2 + (j & 3);
         av[st] = (double)g[2 * cell + (ia >> 3)];
     }
+    // node data of this thread's candidate in the current block, loaded one block ahead so that
+    // the loads overlap the previous block's matrix products
+    int fnode = 0;
+    double fs = 0.0, fsb = 0.0;
+    auto fetch = [&](int bs) {
+        if (bs + k < it.count) {
+            fnode = cand[it.start + bs + k];
+            if (t < kMChunk) {
+                fs = na.s[0][fnode];
+            } else {
+                fs = na.s[1][fnode];
+                if (DIM == 3) fsb = na.s[2][fnode];
+            }
+        }
+    };
+    fetch(0);
     for (int base = 0; base < it.count; base += kMChunk) {
         const int cnt = min(kMChunk, it.count - base);
         if (base > 0) __syncthreads();   // the previous block has read W0T, W1T and nodes
+        const int node_c = fnode;
+        const double s_c = fs, sb_c = fsb;
         if (t < kMChunk) {
             double w0[8];
 #pragma unroll
             for (int x = 0; x < 8; ++x) w0[x] = 0.0;
             int node = 0;
             if (k < cnt) {
-                node = cand[it.start + base + k];
-                tile_weights<MSP, 8>(na.s[0][node], o0, na.Mr[0], na.gc.alpha, qq, w0);
+                node = node_c;
+                tile_weights<MSP, 8>(s_c, o0, na.Mr[0], na.gc.alpha, qq, w0);
             }
             nodes[k] = node;
 #pragma unroll
@@ -779,13 +823,12 @@ __global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict
 #pragma unroll
             for (int j = 0; j < 16; ++j) w1[j] = 0.0;
             if (k < cnt) {
-                const int node = cand[it.start + base + k];
                 if (DIM == 2) {
-                    tile_weights<MSP, 16>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, w1);
+                    tile_weights<MSP, 16>(s_c, o1, na.Mr[1], na.gc.alpha, qq, w1);
                 } else {
                     double a1[4], a2[4];
-                    tile_weights<MSP, 4>(na.s[1][node], o1, na.Mr[1], na.gc.alpha, qq, a1);
-                    tile_weights<MSP, 4>(na.s[2][node], o2, na.Mr[2], na.gc.alpha, qq, a2);
+                    tile_weights<MSP, 4>(s_c, o1, na.Mr[1], na.gc.alpha, qq, a1);
+                    tile_weights<MSP, 4>(sb_c, o2, na.Mr[2], na.gc.alpha, qq, a2);
 #pragma unroll
                     for (int y = 0; y < 4; ++y)
 #pragma unroll
@@ -796,6 +839,7 @@ __global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict
             for (int j = 0; j < 16; ++j) W1T[j][k] = w1[j];
         }
         __syncthreads();
+        fetch(base + kMChunk);
 #pragma unroll
         for (int gi = 0; gi < kMChunk / 64; ++gi) {
             const int k0 = 16 * (wv + 4 * gi);

@@ -107,8 +107,8 @@ def test_split_batched_fields_and_ball_stage_entries():
     pb = nlf.Plan(n, L, nlf.COULOMB3D, split=True, batch=2)
     ub = pb.potential(to_dev(np.stack([r1, r2]), nlf.F64)).cpu().numpy()
     ps = nlf.Plan(n, L, nlf.COULOMB3D, split=True)
-    for i, r in enumerate((r1, r2)):
-        assert rel_err(ub[i], ps.potential(to_dev(r, nlf.F64)).cpu().numpy()) < 1e-13
+    for i, r in enumerate((r1, r2)):   # equal up to the order of the spreading's FP64 atomics
+        assert rel_err(ub[i], ps.potential(to_dev(r, nlf.F64)).cpu().numpy()) < 1e-12
     k, w = ps.nodes()
     assert len(k) == ps.info.n_nodes and np.max(np.linalg.norm(k, axis=1)) <= ps.info.split_P2 * (1 + 1e-12)
     rh = ps.type2(to_dev(r1, nlf.F64)).cpu().numpy()
