@@ -49,6 +49,7 @@ struct GItem {
     int g0, g1, g2;    // tile coordinates
     int count;         // candidates in this item
     long long start;   // first entry in the candidate list
+    int only;          // 1: the tile's only item (the spreading stores its sums instead of adding)
 };
 constexpr int kMChunk = 128;
 constexpr int kMItem = 1024;

@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
 #pragma unroll
         for (int w = 0; w < NW; ++w) sum += S[(w * 4 + v) * 64 + l];
         const int i = 4 * v + (l >> 4), j = l & 15;
-        if (sum != 0.0) {
+        if (it.only || sum != 0.0) {
             const int x = o0 + (i & 7);
             long long cell;
             if (DIM == 2)
@@ -585,7 +585,9 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
             else
                 cell = ((long long)x * na.Mr[1] + o1 + (j >> 2)) * na.Mr[2] + o2 + (j & 3);
             TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride + cell) + (i >> 3);
-            global_add<TG>(dst, (TG)sum);
+            // the tile's only item owns its cells: a plain store; otherwise one atomic per item
+            if (it.only) *dst = (TG)sum;
+            else global_add<TG>(dst, (TG)sum);
         }
     }
 }

@@ -41,6 +41,7 @@ int set_items(nlf_plan* p, int cap, bool bins) {
             it.g2 = g2;
             it.count = (int)std::min<long long>(cap, end - s0);
             it.start = bins ? s0 - beg : s0;   // bins: offset within the tile's candidate stream
+            it.only = (end - beg <= cap) ? 1 : 0;
             items.push_back(it);
         }
     }
