@@ -50,8 +50,7 @@ __device__ __forceinline__ int dmap(int j, int nd, int Mr) {
 __device__ __forceinline__ bool is_data_row(int r, int nd, int Mr) { return r < nd / 2 || r >= Mr - nd / 2; }
 
 // In-place multi-line Stockham FFT of nl lines of length n = 2^lg held in buf[line*pitch + i].
-// tw[t] = exp(-2 pi i t / n).  DIR = -1 forward, +1 inverse (unnormalised).
-// Mixed radix: one radix-2 or radix-4 pass first when lg is not a multiple of 3, then radix-8
+// tw[t] = exp(-2 pi i t / n).  DIR = -1 forward, +1 inverse (unnormalised).  Mixed radix: one radix-2 or radix-4 pass first when lg is not a multiple of 3, then radix-8
 // passes, each a read of the whole buffer into registers and a write back (fewer LDS round trips
 // than radix 4: 512 points take 3 passes instead of 5).  Pass with radix R over the index range
 // q = n / R, after p = product of the earlier radices: butterfly i (k = i mod p) reads
@@ -99,7 +98,7 @@ __device__ __forceinline__ void dft8(V2<T> (&a)[8]) {
     a[7] = csub<T>(e3, o3);
 }
 
-template <typename T, int DIR, int NT, int E, int R>
+template <typename T, int DIR, int NT, int E, int R, bool HALF>
 __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, int p, const V2<T>* __restrict__ tw) {
     constexpr int RB = (E + R * NT - 1) / (R * NT);   // butterflies per thread
     const int q = n / R;
@@ -119,7 +118,14 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
             if (p > 1) {
 #pragma unroll
                 for (int m = 1; m < R; ++m) {
-                    V2<T> w = tw[m * k * tstep];
+                    const int tt = m * k * tstep;
+                    V2<T> w;
+                    if constexpr (HALF) {   // half table (in LDS): w^(t + n/2) = -w^t
+                        w = tw[tt < (n >> 1) ? tt : tt - (n >> 1)];
+                        if (tt >= (n >> 1)) { w.x = -w.x; w.y = -w.y; }
+                    } else {
+                        w = tw[tt];
+                    }
                     if (DIR > 0) w.y = -w.y;
                     y[r][m] = cmul<T>(y[r][m], w);
                 }
@@ -152,18 +158,19 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
     __syncthreads();
 }
 
-template <typename T, int DIR, int NT, int E>
+// HALF: tw holds w^t for t < n/2 only (the LDS copy); otherwise the full table
+template <typename T, int DIR, int NT, int E, bool HALF = false>
 __device__ void lds_fft(V2<T>* buf, int pitch, int n, int lg, int nl, const V2<T>* __restrict__ tw) {
     int p = 1;
     if (lg % 3 == 1) {
-        fft_pass<T, DIR, NT, E, 2>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 2, HALF>(buf, pitch, n, nl, p, tw);
         p = 2;
     } else if (lg % 3 == 2) {
-        fft_pass<T, DIR, NT, E, 4>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 4, HALF>(buf, pitch, n, nl, p, tw);
         p = 4;
     }
     while (p < n) {
-        fft_pass<T, DIR, NT, E, 8>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 8, HALF>(buf, pitch, n, nl, p, tw);
         p *= 8;
     }
 }
@@ -210,7 +217,9 @@ __device__ __forceinline__ double wg_sum(double v, double* sh16) {
     return s;
 }
 
-template <typename T, typename TIO, int DIR, int LOAD, int STORE, int E>
+// TWL: the twiddle table is staged in LDS (short lines, n <= 512) or read from global memory
+// through the L1 cache (longer lines: measured faster for the 1024-point columns of the 2D grids)
+template <typename T, typename TIO, int DIR, int LOAD, int STORE, int E, bool TWL>
 __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
@@ -240,6 +249,15 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
         return (long long)dmap(j0, a.nd[0], a.Mr[0]) * a.Mr[1] + dmap(j1, a.nd[1], a.Mr[1]);
     };
     const double* decl = (a.dim == 2) ? a.dec1 : a.dec2;
+    // the line's twiddle table, staged in LDS after the data (read by every FFT pass)
+    V2<T>* twl = buf + a.lines_per_wg * pitch;
+    constexpr int PERT = (E + NT - 1) / NT;
+    V2<T> tv[PERT];
+#pragma unroll
+    for (int u = 0; u < PERT; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (TWL && i < (n >> 1)) tv[u] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    }
 
     // ---- load
     if (LOAD == LOAD_RHO) {
@@ -317,8 +335,13 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
             if (idx < nl * n) buf[(idx / n) * pitch + idx % n] = v[u];
         }
     }
+#pragma unroll
+    for (int u = 0; u < PERT; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (TWL && i < (n >> 1)) twl[i] = tv[u];
+    }
     __syncthreads();
-    lds_fft<T, DIR, NT, E>(buf, pitch, n, a.lg, nl, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, E, TWL>(buf, pitch, n, a.lg, nl, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
 
     // ---- store
     if (STORE == STORE_GRID) {
@@ -395,7 +418,7 @@ __device__ __forceinline__ long long band_col(const ColsArgs& a, int cb) {
     return (long long)c1 * a.Mr2 + c2;
 }
 
-template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E>
+template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E, bool TWL>
 __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
@@ -425,9 +448,11 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     long long go = a.outer_mapped ? dmap(o, a.outer_nd, a.outer_Mr) : o;
     V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride +
                   go * (long long)n * a.inner + band_col(a, cb);
-    // every load of the thread is issued before the first LDS write (one memory latency, not PER)
+    // every load of the thread (data and the twiddle table, which is staged in LDS after the
+    // data) is issued before the first LDS write: one memory latency, not PER
     constexpr int PER = (E + NT - 1) / NT;
-    V2<T> v[PER];
+    V2<T> v[PER], tv[PER];
+    V2<T>* twl = buf + C * pitch;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
@@ -436,14 +461,16 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
             const int r = idx / C, c = idx - r * C;
             if (!LPRUNE || is_data_row(r, a.nd, n)) v[u] = base[(long long)r * a.inner + c];
         }
+        if (TWL && idx < (n >> 1)) tv[u] = reinterpret_cast<const V2<T>*>(a.tw)[idx];
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
         if (idx < n * C) buf[(idx % C) * pitch + idx / C] = v[u];
+        if (TWL && idx < (n >> 1)) twl[idx] = tv[u];
     }
     __syncthreads();
-    lds_fft<T, DIR, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     const int nds = a.nd_store > 0 ? a.nd_store : a.nd;
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
@@ -460,7 +487,7 @@ struct ConvW {
     double dk0, dk1, dk2, inva;
 };
 
-template <typename T, int NT, int E>
+template <typename T, int NT, int E, bool TWL>
 __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
@@ -472,7 +499,8 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
     const long long col0 = (long long)cb * C;
     V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride + col0;
     constexpr int PER = (E + NT - 1) / NT;
-    V2<T> v[PER];
+    V2<T> v[PER], tv[PER];
+    V2<T>* twl = buf + C * pitch;   // twiddles staged in LDS after the data
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
@@ -481,14 +509,16 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
             const int r = idx / C, c = idx - r * C;
             if (is_data_row(r, a.nd, n)) v[u] = base[(long long)r * a.inner + c];
         }
+        if (TWL && idx < (n >> 1)) tv[u] = reinterpret_cast<const V2<T>*>(a.tw)[idx];
     }
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
         if (idx < n * C) buf[(idx % C) * pitch + idx / C] = v[u];
+        if (TWL && idx < (n >> 1)) twl[idx] = tv[u];
     }
     __syncthreads();
-    lds_fft<T, -1, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, -1, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     __syncthreads();
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
@@ -505,7 +535,7 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
         buf[c * pitch + r] = v;
     }
     __syncthreads();
-    lds_fft<T, 1, NT, E>(buf, pitch, n, a.lg, C, reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, 1, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     __syncthreads();
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
@@ -541,21 +571,21 @@ static int ilog2(int v) {
     return l;
 }
 
-template <typename T, int DIR, int LOAD, int STORE, typename TIO, int E>
+template <typename T, int DIR, int LOAD, int STORE, typename TIO, int E, bool TWL>
 static int launch_rows_cfg(nlf_plan* p, RowsArgs a, int batch) {
     constexpr int NT = RowCfg::NT;
     a.lg = ilog2(a.n);
     a.lines_per_wg = std::max(1, E / a.n);
     if (a.n > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
     dim3 grid((a.nlines + a.lines_per_wg - 1) / a.lines_per_wg, batch);
-    size_t lds = (size_t)a.lines_per_wg * a.n * sizeof(V2<T>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, E * (int)sizeof(V2<T>)));
-        attr_set = true;
+    size_t lds = ((size_t)a.lines_per_wg * a.n + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // lines (+ twiddles)
+    static size_t attr_bytes = 0;
+    if (lds > attr_bytes) {
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_bytes = lds;
     }
-    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE, E>), grid, dim3(NT), lds, p->stream, a);
+    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -567,11 +597,12 @@ static int rows_lines_per_wg(int n) { return std::max(1, rows_budget(n) / n); }
 
 template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
 static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
-    if (rows_budget(a.n) == 1024) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, 1024>(p, a, batch);
-    return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E>(p, a, batch);
+    if (rows_budget(a.n) == 1024) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, 1024, false>(p, a, batch);
+    if (a.n <= 512) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, true>(p, a, batch);
+    return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, false>(p, a, batch);
 }
 
-template <typename T, int DIR, bool LP, bool SP, int NT, int E>
+template <typename T, int DIR, bool LP, bool SP, int NT, int E, bool TWL>
 static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     a.lg = ilog2(a.n);
     // C adjacent columns per workgroup: as many as the element budget E allows (the padded pitch
@@ -588,14 +619,14 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
         return set_error(NLF_EINVAL, "column band %d/%d does not fit the grid", a.bc1, a.bc2);
     a.ncb = a.bc2 ? (a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / C) : (int)(a.inner / C);
     dim3 grid(a.ncb, outer, batch);
-    size_t lds = (size_t)C * (a.n + 1) * sizeof(V2<T>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP, NT, E>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (E + 16) * (int)sizeof(V2<T>)));
-        attr_set = true;
+    size_t lds = ((size_t)C * (a.n + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
+    static size_t attr_bytes = 0;
+    if (lds > attr_bytes) {
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP, NT, E, TWL>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_bytes = lds;
     }
-    hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP, NT, E>), grid, dim3(NT), lds, p->stream, a);
+    hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP, NT, E, TWL>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -603,11 +634,11 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
 template <typename T, int DIR, bool LP, bool SP>
 static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
     if (a.n <= 512)
-        return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E>(p, a, outer, batch);
-    return launch_cols_cfg<T, DIR, LP, SP, FftCfg<T>::NT, FftCfg<T>::E>(p, a, outer, batch);
+        return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E, true>(p, a, outer, batch);
+    return launch_cols_cfg<T, DIR, LP, SP, FftCfg<T>::NT, FftCfg<T>::E, false>(p, a, outer, batch);
 }
 
-template <typename T, int NT, int E>
+template <typename T, int NT, int E, bool TWL>
 static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     a.lg = ilog2(a.n);
     int C = 16;   // as in launch_cols_cfg
@@ -616,14 +647,14 @@ static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     a.C = C;
     a.ncb = (int)(a.inner / C);
     dim3 grid(a.ncb, 1, batch);
-    size_t lds = (size_t)C * (a.n + 1) * sizeof(V2<T>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0<T, NT, E>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (E + 16) * (int)sizeof(V2<T>)));
-        attr_set = true;
+    size_t lds = ((size_t)C * (a.n + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
+    static size_t attr_bytes = 0;
+    if (lds > attr_bytes) {
+        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0<T, NT, E, TWL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+        attr_bytes = lds;
     }
-    hipLaunchKernelGGL((k_fft_conv0<T, NT, E>), grid, dim3(NT), lds, p->stream, a, cw);
+    hipLaunchKernelGGL((k_fft_conv0<T, NT, E, TWL>), grid, dim3(NT), lds, p->stream, a, cw);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -660,8 +691,8 @@ static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
     cw.dk0 = 2.0 * 3.14159265358979323846 / (p->Mr[0] * p->h[0]);
     cw.dk1 = 2.0 * 3.14159265358979323846 / (p->Mr[1] * p->h[1]);
     cw.dk2 = 2.0 * 3.14159265358979323846 / (p->Mr[2] * p->h[2]);
-    if (c0.n <= 512) NLF_TRY((launch_conv0_cfg<T, ColSmallCfg::NT, ColSmallCfg::E>(p, c0, cw, p->batch)));
-    else NLF_TRY((launch_conv0_cfg<T, FftCfg<T>::NT, FftCfg<T>::E>(p, c0, cw, p->batch)));
+    if (c0.n <= 512) NLF_TRY((launch_conv0_cfg<T, ColSmallCfg::NT, ColSmallCfg::E, true>(p, c0, cw, p->batch)));
+    else NLF_TRY((launch_conv0_cfg<T, FftCfg<T>::NT, FftCfg<T>::E, false>(p, c0, cw, p->batch)));
     c.nd = p->n[1];
     NLF_TRY((launch_cols<T, 1, false, true>(p, c, p->n[0], p->batch)));
     RowsArgs ri = r;
