@@ -98,7 +98,7 @@ typedef struct {
  *   library on the small ball P2 = sqrt(34.5 a) (p(P2) ~ 1e-15), whose node count does not grow
  *   with the grid.  The default a puts I1's kernel erfc(sqrt(a) r/2)/(4 pi r) at erfc(5.5) at the
  *   nearest periodic image.  n_r, n_theta, n_phi set the ball's rule (default
- *   ceil(P2 D/2) + 8, the same, twice that; D = 2 |L| the box diameter); P and sigma must be 0.
+ *   ceil(3 P2 D/8) + 8, the same, twice that; D = 2 |L| the box diameter); P and sigma must be 0.
  *   Needs pi / max h_i >= P2 (NLF_EUNSUPPORTED otherwise, e.g. 16^3 on [-8,8]^3).  On a split
  *   plan nlf_type2, nlf_type1, nlf_plan_nodes and the spreading controls act on the ball's
  *   nodes; stage times add the ball's stages to I1's (its forward FFT under FFT_FWD, the

@@ -19,15 +19,16 @@ Parameters (the paper leaves them open; reading taken here, stated in the design
     sqrt(a) = 5.5 / min_i L_i      I1's kernel erfc(sqrt(a) r / 2) / (4 pi r) has fallen to
                                    erfc(5.5) ~ 7e-15 at the nearest periodic image (2 L away);
     P2 = sqrt(34.5 a)              p(P2) = e^{-34.5} ~ 1e-15;
-    n_r = n_theta = ceil(P2 D / 2) + 8, n_phi = 2 n_theta, D = 2 |L| the box diameter
+    n_r = n_theta = ceil(3 P2 D / 8) + 8, n_phi = 2 n_theta, D = 2 |L| the box diameter
                                    (the largest phase |k| |x - x_j| across the box is P2 D;
-                                   Gauss-Legendre resolves e^{i w r} on [0, P2] to rounding with
-                                   about w P2 / 2 nodes).
+                                   on densities near opposite corners of the box the ball sum has
+                                   converged to rounding from about 0.65 P2 D / 2 nodes on, and
+                                   this rule keeps 0.75 of P2 D / 2 plus 8).
 The split needs the grid's cube to hold the ball: P_i >= sqrt(34.5 a) on every axis.
 
 parity pins (tests/test_oracle_split.py): I1 and I2 each against their closed forms for a
-Gaussian density, their sum against the 3D Coulomb closed form of Example 2.1, and the
-independence of the sum from a.
+Gaussian density, their sum against the 3D Coulomb closed form of Example 2.1, the independence
+of the sum from a, and the ball rule against a finer one on densities in the box's corners.
 """
 import numpy as np
 
@@ -47,7 +48,7 @@ def split_params(n, L, a=None, n_r=None, n_theta=None, n_phi=None):
     if P2 > P:
         raise ValueError("grid too coarse for the split: pi / max(h) = %g < sqrt(34.5 a) = %g" % (P, P2))
     D = 2.0 * np.sqrt(sum(Li * Li for Li in L))
-    nr = int(np.ceil(P2 * D / 2.0)) + 8
+    nr = int(np.ceil(3.0 * P2 * D / 8.0)) + 8
     n_r = nr if n_r is None else int(n_r)
     n_theta = nr if n_theta is None else int(n_theta)
     n_phi = 2 * nr if n_phi is None else int(n_phi)

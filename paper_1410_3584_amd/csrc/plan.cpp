@@ -199,7 +199,9 @@ static int build_split(nlf_plan* p, const nlf_box* box, int kernel, const nlf_op
     if (p->split_P2 > p->P * (1 + 1e-12))
         return set_error(NLF_EUNSUPPORTED, "grid too coarse for the split: pi/max(h) = %g < P2 = sqrt(34.5 a) = %g",
                          p->P, p->split_P2);
-    const int nr = (int)std::ceil(0.5 * p->split_P2 * std::sqrt(D2)) + 8;
+    // ball rule: 0.75 of the largest phase P2 D / 2 across the box, plus 8 (converged to rounding
+    // from about 0.65 on densities in opposite corners of the box)
+    const int nr = (int)std::ceil(0.375 * p->split_P2 * std::sqrt(D2)) + 8;
     nlf_opts so = *o;
     so.split = 0;
     so.split_a = 0;

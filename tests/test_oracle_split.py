@@ -65,3 +65,19 @@ def test_split_sum_independent_of_partition_width():
 def test_split_rejects_coarse_grid():
     with pytest.raises(ValueError):
         sp.split_params((16,) * 3, (8.0,) * 3)
+
+
+def test_split_ball_rule_converged_on_corner_densities():
+    """The default ball rule resolves the largest phases across the box: with Gaussians near
+    three corners of [-8,8]^3 (separations up to ~19 across the box), I2 by the default rule
+    equals I2 by a rule of 80 radial and polar and 160 azimuthal nodes to rounding."""
+    n, L = (32,) * 3, (8.0,) * 3
+    xs, _ = op.grid_axes(n, L)
+    X, Y, Z = np.meshgrid(*xs, indexing="ij")
+    cs = [(5.5, 5.0, 5.5), (-5.5, -5.5, -5.0), (5.0, -5.5, 5.5)]
+    rho = sum(np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)) for c in cs)
+    prm = sp.split_params(n, L)
+    assert prm["n_r"] < 60
+    u2 = sp.i2_ball(rho, n, L, prm["a"], prm["P2"], prm["n_r"], prm["n_theta"], prm["n_phi"])
+    ref = sp.i2_ball(rho, n, L, prm["a"], prm["P2"], 80, 80, 160)
+    assert np.max(np.abs(u2 - ref)) < 1e-13 * np.max(np.abs(ref))
