@@ -40,6 +40,20 @@ def test_split_parity_with_oracle(prec):
     assert rel_err(u, want) <= TOL[prec]
 
 
+def test_split_parity_non_cubic_box():
+    """A box with unequal sides (32^3 on [-8,8]x[-8,8]x[-6,6]): the partition width follows the
+    shortest side and the ball rule the box diameter, on both sides, element by element."""
+    n, L = (32,) * 3, (8.0, 8.0, 6.0)
+    print(f"[split parity] n={n} L={L}", flush=True)
+    rho = _density(n, L)
+    plan = nlf.Plan(n, L, nlf.COULOMB3D, split=True)
+    prm = sp.split_params(n, L)
+    assert abs(plan.info.split_a - prm["a"]) < 1e-15
+    assert plan.info.n_nodes == prm["n_r"] * prm["n_theta"] * prm["n_phi"]
+    u = plan.potential(to_dev(rho, nlf.F64)).cpu().numpy()
+    assert rel_err(u, sp.split_potential(rho, n, L)) <= TOL[nlf.F64]
+
+
 def test_split_closed_form_128():
     """rho = exp(-|x|^2/1.5^2) on 128^3 of [-12,12]^3: Example 2.1's closed form at every grid
     point."""
