@@ -107,6 +107,43 @@ __device__ __forceinline__ void coords(const Geo& g, long long i, double x[3], i
     }
 }
 // |mu|^2 of the discrete Fourier mode at flat index i (mu_l = pi l / L, l in [-n/2, n/2))
+// linear index of the frequency -k of linear index i (per axis l -> (n - l) mod n)
+__device__ __forceinline__ long long neg_index(const Geo& g, long long i) {
+    long long r = i, out = 0, mul = 1;
+    for (int a = g.dim - 1; a >= 0; --a) {
+        const int l = (int)(r % g.n[a]);
+        r /= g.n[a];
+        out += (long long)(l ? g.n[a] - l : 0) * mul;
+        mul *= g.n[a];
+    }
+    return out;
+}
+
+// The residuals of fields 2q and 2q+1 share one complex transform, z = r_2q + i r_2q+1 (both real):
+// field b writes its part of z, and reads its own spectrum back as (Z(k) + conj Z(-k)) / 2 (even b)
+// or (Z(k) - conj Z(-k)) / (2i) (odd b).  The extraction is exact for any real other part, but that
+// part must stay of the residuals' size: after the transform the buffer holds a spectrum, so a field
+// whose partner is not writing this iteration (retired, or absent in an odd batch) clears the
+// partner's part (lone = true).
+template <typename T>
+__device__ __forceinline__ void put_resid(V2<T>* zf, long long N, int b, long long i, T v, bool lone) {
+    V2<T>* z = zf + (long long)(b >> 1) * N + i;
+    if (lone) *z = (b & 1) ? mkc<T>((T)0, v) : mkc<T>(v, (T)0);
+    else reinterpret_cast<T*>(z)[b & 1] = v;
+}
+template <typename T>
+__device__ __forceinline__ void pair_spec(const V2<T>* zf, long long N, int b, long long i, long long ni, double& re,
+                                          double& im) {
+    const V2<T> z = zf[(long long)(b >> 1) * N + i], zm = zf[(long long)(b >> 1) * N + ni];
+    if ((b & 1) == 0) {
+        re = 0.5 * ((double)z.x + (double)zm.x);
+        im = 0.5 * ((double)z.y - (double)zm.y);
+    } else {
+        re = 0.5 * ((double)z.y + (double)zm.y);
+        im = -0.5 * ((double)z.x - (double)zm.x);
+    }
+}
+
 __device__ __forceinline__ double mu2(const Geo& g, long long i) {
     long long r = i;
     double s = 0;
@@ -283,9 +320,10 @@ __global__ void k_shift(Fld* fl, const double* part_mx, const double* part_mn, i
     }
 }
 
-// PCG start: x = phi, r = b - A x = -(K phi + W phi) (with b = phi/tau), cw = (r, 0); bb, rr partials
+// PCG start: x = phi, r = b - A x = -(K phi + W phi) (with b = phi/tau), r into its pair
+// transform zf; bb partials
 template <typename T>
-__global__ void k_pcg_init(Geo g, Fld* fl, const T* phi, const T* W, const V2<T>* kphi, T* x, T* r, V2<T>* cw,
+__global__ void k_pcg_init(Geo g, Fld* fl, const T* phi, const T* W, const V2<T>* kphi, T* x, T* r, V2<T>* zf,
                            double* part_bb) {
     const int b = blockIdx.y;
     if (fl[b].done) return;
@@ -294,6 +332,8 @@ __global__ void k_pcg_init(Geo g, Fld* fl, const T* phi, const T* W, const V2<T>
     // current chemical potential mu): r0 = (1 - c) phi/tau - c H phi = c (mu phi - H phi), the
     // eigen-residual, which vanishes as the flow converges.  The first step starts from phi^n.
     const double c = (fl[b].steps > 0 && fl[b].norm2 > 0.0) ? sqrt(fl[b].norm2) : 1.0;
+    // the partner field runs this kernel too unless it has retired from the flow or is absent
+    const bool lone = ((b ^ 1) >= (int)gridDim.y) || fl[b ^ 1].done;
     double s = 0;
     for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
         long long k = (long long)b * g.N + i;
@@ -301,7 +341,7 @@ __global__ void k_pcg_init(Geo g, Fld* fl, const T* phi, const T* W, const V2<T>
         double ri = (1.0 - c) * p / tau - c * ((double)kphi[k].x + (double)W[k] * p);
         x[k] = (T)(c * p);
         r[k] = (T)ri;
-        cw[k] = mkc<T>((T)ri, (T)0);
+        put_resid<T>(zf, g.N, b, i, (T)ri, lone);
         s += (p / tau) * (p / tau);
     }
     s = block_sum(s);
@@ -321,17 +361,18 @@ __global__ void k_bb_final(Fld* fl, const double* part_bb, int nblk) {
     if (threadIdx.x == 0) fl[b].bb = s;
 }
 
-// rz = sum D |r^|^2 / N (Parseval), D = 1/(1/tau + a + K)
+// rz = sum D |r^|^2 / N (Parseval), D = 1/(1/tau + a + K); r^ from the pair transform zf
 template <typename T>
-__global__ void k_pcg_rz(Geo g, const Fld* fl, const V2<T>* cw, double* part_rz) {
+__global__ void k_pcg_rz(Geo g, const Fld* fl, const V2<T>* zf, double* part_rz) {
     const int b = blockIdx.y;
     if (fl[b].done || fl[b].conv) return;
     const double c0 = 1.0 / fl[b].tau + fl[b].a;
     double s = 0;
     for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
-        V2<T> v = cw[(long long)b * g.N + i];
+        double vx, vy;
+        pair_spec<T>(zf, g.N, b, i, neg_index(g, i), vx, vy);
         double d = 1.0 / (c0 + 0.5 * mu2(g, i));
-        s += d * ((double)v.x * v.x + (double)v.y * v.y);
+        s += d * (vx * vx + vy * vy);
     }
     s = block_sum(s);
     if (threadIdx.x == 0) part_rz[b * MAXBLK + blockIdx.x] = s / (double)g.N;
@@ -339,7 +380,7 @@ __global__ void k_pcg_rz(Geo g, const Fld* fl, const V2<T>* cw, double* part_rz)
 
 // p^ = D r^ + beta p^ (beta = rz / rz_old), cw = (p^ + i K p^) / N for the inverse transform
 template <typename T>
-__global__ void k_pcg_dir(Geo g, Fld* fl, V2<T>* cw, V2<T>* ph, const double* part_rz, int nblk) {
+__global__ void k_pcg_dir(Geo g, Fld* fl, const V2<T>* zf, V2<T>* cw, V2<T>* ph, const double* part_rz, int nblk) {
     const int b = blockIdx.y;
     if (fl[b].done || fl[b].conv) return;
     const double rz = sum_parts(part_rz + b * MAXBLK, nblk);
@@ -351,8 +392,9 @@ __global__ void k_pcg_dir(Geo g, Fld* fl, V2<T>* cw, V2<T>* ph, const double* pa
         long long k = (long long)b * g.N + i;
         double m2 = mu2(g, i);
         double d = 1.0 / (c0 + 0.5 * m2);
-        V2<T> rv = cw[k];
-        double px = d * (double)rv.x, py = d * (double)rv.y;
+        double rx, ry;
+        pair_spec<T>(zf, g.N, b, i, neg_index(g, i), rx, ry);
+        double px = d * rx, py = d * ry;
         if (beta != 0.0) {   // the previous direction is never read on a restart (it may be unset)
             V2<T> pv = ph[k];
             px += beta * (double)pv.x;
@@ -386,9 +428,9 @@ __global__ void k_pcg_apply(Geo g, const Fld* fl, const V2<T>* cw, const T* W, T
     if (threadIdx.x == 0) part_pap[b * MAXBLK + blockIdx.x] = s;
 }
 
-// a = rz / pAp; x += a p; r -= a Ap; cw = (r, 0); rr partials
+// a = rz / pAp; x += a p; r -= a Ap; r into its pair transform zf; rr partials
 template <typename T>
-__global__ void k_pcg_update(Geo g, const Fld* fl, const T* p, const T* Ap, T* x, T* r, V2<T>* cw,
+__global__ void k_pcg_update(Geo g, const Fld* fl, const T* p, const T* Ap, T* x, T* r, V2<T>* zf,
                              const double* part_pap, double* part_rr, int nblk) {
     const int b = blockIdx.y;
     if (fl[b].done || fl[b].conv) return;
@@ -400,6 +442,9 @@ __global__ void k_pcg_update(Geo g, const Fld* fl, const T* p, const T* Ap, T* x
         return;
     }
     const double al = fl[b].rz / pap;
+    // the partner writes its residual this iteration unless retired (flow or inner solve) or absent;
+    // its conv flag only changes in k_pcg_check, after this kernel
+    const bool lone = ((b ^ 1) >= (int)gridDim.y) || fl[b ^ 1].done || fl[b ^ 1].conv;
     double s = 0;
     for (long long i = (long long)blockIdx.x * RB_T + threadIdx.x; i < g.N; i += (long long)gridDim.x * RB_T) {
         long long k = (long long)b * g.N + i;
@@ -407,7 +452,7 @@ __global__ void k_pcg_update(Geo g, const Fld* fl, const T* p, const T* Ap, T* x
         double rv = (double)r[k] - al * (double)Ap[k];
         x[k] = (T)xv;
         r[k] = (T)rv;
-        cw[k] = mkc<T>((T)rv, (T)0);
+        put_resid<T>(zf, g.N, b, i, (T)rv, lone);
         s += rv * rv;
     }
     s = block_sum(s);
@@ -547,6 +592,7 @@ struct SolverWs {
     void* pot = nullptr;
     void* cw = nullptr;    // complex [B][N]
     void* ph = nullptr;    // complex [B][N]
+    void* zf = nullptr;    // complex [(B+1)/2][N]: residual transforms of field pairs
     Fld* fl = nullptr;
     double* part = nullptr;    // 8 arrays of [B][MAXBLK]
     double* epart = nullptr;   // [B][MAXBLK][4]
@@ -565,6 +611,8 @@ static int ws_get(nlf_plan* p, SolverWs& w) {
     NLF_TRY(dev_alloc(p, &w.pot, B * N * es));
     NLF_TRY(dev_alloc(p, &w.cw, B * N * ec));
     NLF_TRY(dev_alloc(p, &w.ph, B * N * ec));
+    NLF_TRY(dev_alloc(p, &w.zf, (B + 1) / 2 * N * ec));
+    NLF_HIP(hipMemset(w.zf, 0, (B + 1) / 2 * N * ec));   // the unpaired half of an odd batch stays 0
     NLF_TRY(dev_alloc(p, (void**)&w.fl, B * sizeof(Fld)));
     NLF_TRY(dev_alloc(p, (void**)&w.part, 8 * B * MAXBLK * sizeof(double)));
     NLF_TRY(dev_alloc(p, (void**)&w.epart, B * MAXBLK * 4 * sizeof(double)));
@@ -818,7 +866,7 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
         hipLaunchKernelGGL((k_kin_apply<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (V2<T>*)w.cw);
         NLF_TRY(fft_full(p, w.cw, 1, B));
         hipLaunchKernelGGL((k_pcg_init<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.phi, (const T*)w.W,
-                           (const V2<T>*)w.cw, (T*)w.x, (T*)w.r, (V2<T>*)w.cw, part_bb);
+                           (const V2<T>*)w.cw, (T*)w.x, (T*)w.r, (V2<T>*)w.zf, part_bb);
         hipLaunchKernelGGL(k_bb_final, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_bb, nb);
         NLF_HIP(hipGetLastError());
         return NLF_OK;
@@ -826,15 +874,15 @@ static int ground_state_t(nlf_plan* p, const nlf_phys* phys, const GsParams& gp,
     // one inner iteration (fields whose solve converged skip the pointwise kernels)
     auto cg_block = [&]() -> int {
         {
-            NLF_TRY(fft_full(p, w.cw, -1, B));
-            hipLaunchKernelGGL((k_pcg_rz<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.cw, part_rz);
-            hipLaunchKernelGGL((k_pcg_dir<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (V2<T>*)w.cw, (V2<T>*)w.ph,
-                               part_rz, nb);
+            NLF_TRY(fft_full(p, w.zf, -1, (B + 1) / 2));   // residuals of field pairs
+            hipLaunchKernelGGL((k_pcg_rz<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.zf, part_rz);
+            hipLaunchKernelGGL((k_pcg_dir<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.zf,
+                               (V2<T>*)w.cw, (V2<T>*)w.ph, part_rz, nb);
             NLF_TRY(fft_full(p, w.cw, 1, B));
             hipLaunchKernelGGL((k_pcg_apply<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const V2<T>*)w.cw,
                                (const T*)w.W, (T*)w.p, (T*)w.Ap, part_pap);
             hipLaunchKernelGGL((k_pcg_update<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, (const T*)w.p,
-                               (const T*)w.Ap, (T*)w.x, (T*)w.r, (V2<T>*)w.cw, part_pap, part_rr, nb);
+                               (const T*)w.Ap, (T*)w.x, (T*)w.r, (V2<T>*)w.zf, part_pap, part_rr, nb);
             hipLaunchKernelGGL(k_pcg_check, dim3(B), dim3(RB_T), 0, p->stream, w.fl, part_rr, nb);
             NLF_HIP(hipGetLastError());
         }
