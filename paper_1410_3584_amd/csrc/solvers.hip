@@ -93,28 +93,30 @@ __device__ double max_parts_neg(const double* part, int nblk) {
 struct Geo {
     int dim;
     int n[3];
+    int lg[3];        // log2 n_i (grid sizes are powers of two)
     double L[3], h[3];
     long long N;
     double dv;        // prod h_i
 };
 
+// per-axis indices by shifts and masks (no 64-bit division per element)
 __device__ __forceinline__ void coords(const Geo& g, long long i, double x[3], int j[3]) {
     long long r = i;
     for (int a = g.dim - 1; a >= 0; --a) {
-        j[a] = (int)(r % g.n[a]);
-        r /= g.n[a];
+        j[a] = (int)(r & (g.n[a] - 1));
+        r >>= g.lg[a];
         x[a] = -g.L[a] + j[a] * g.h[a];
     }
 }
-// |mu|^2 of the discrete Fourier mode at flat index i (mu_l = pi l / L, l in [-n/2, n/2))
 // linear index of the frequency -k of linear index i (per axis l -> (n - l) mod n)
 __device__ __forceinline__ long long neg_index(const Geo& g, long long i) {
-    long long r = i, out = 0, mul = 1;
+    long long r = i, out = 0;
+    int sh = 0;
     for (int a = g.dim - 1; a >= 0; --a) {
-        const int l = (int)(r % g.n[a]);
-        r /= g.n[a];
-        out += (long long)(l ? g.n[a] - l : 0) * mul;
-        mul *= g.n[a];
+        const int l = (int)(r & (g.n[a] - 1));
+        r >>= g.lg[a];
+        out |= (long long)((g.n[a] - l) & (g.n[a] - 1)) << sh;
+        sh += g.lg[a];
     }
     return out;
 }
@@ -144,12 +146,13 @@ __device__ __forceinline__ void pair_spec(const V2<T>* zf, long long N, int b, l
     }
 }
 
+// |mu|^2 of the discrete Fourier mode at flat index i (mu_l = pi l / L, l in [-n/2, n/2))
 __device__ __forceinline__ double mu2(const Geo& g, long long i) {
     long long r = i;
     double s = 0;
     for (int a = g.dim - 1; a >= 0; --a) {
-        int l = (int)(r % g.n[a]);
-        r /= g.n[a];
+        int l = (int)(r & (g.n[a] - 1));
+        r >>= g.lg[a];
         if (l >= g.n[a] / 2) l -= g.n[a];
         double m = 3.14159265358979323846 * l / g.L[a];
         s += m * m;
@@ -628,6 +631,8 @@ static Geo geo_of(const nlf_plan* p) {
         g.n[i] = p->n[i];
         g.L[i] = p->L[i];
         g.h[i] = p->h[i];
+        g.lg[i] = 0;
+        while ((1 << g.lg[i]) < p->n[i]) ++g.lg[i];
     }
     for (int i = 0; i < p->dim; ++i) g.dv *= p->h[i];
     return g;
@@ -1000,13 +1005,16 @@ static int evolve_t(nlf_plan* p, const nlf_phys* phys, const nlf_ts_opts* ts, vo
     }
     NLF_HIP(hipMemcpyAsync(w.fl, fh.data(), B * sizeof(Fld), hipMemcpyHostToDevice, p->stream));
     const dim3 grid(nb, B);
+    // the phase kernels reduce nothing: as many blocks as the grid needs (up to 4096 per field),
+    // not the MAXBLK of the reductions, so that large grids keep enough waves in flight
+    const dim3 pgrid((unsigned)std::min<long long>((g.N + RB_T - 1) / RB_T, 4096), B);
     const long long cnt = (long long)B * g.N;
     double pending = 0.0;   // kinetic time not yet applied (adjacent half steps are merged)
 
     auto flush_kin = [&]() -> int {
         if (pending != 0.0) {
             NLF_TRY(fft_full(p, psi, -1, B));
-            hipLaunchKernelGGL((k_kin_phase<T>), grid, dim3(RB_T), 0, p->stream, g, B, (V2<T>*)psi, pending);
+            hipLaunchKernelGGL((k_kin_phase<T>), pgrid, dim3(RB_T), 0, p->stream, g, B, (V2<T>*)psi, pending);
             NLF_HIP(hipGetLastError());
             NLF_TRY(fft_full(p, psi, 1, B));
             pending = 0.0;
@@ -1019,7 +1027,7 @@ static int evolve_t(nlf_plan* p, const nlf_phys* phys, const nlf_ts_opts* ts, vo
         hipLaunchKernelGGL((k_density<T>), flat_grid(cnt), dim3(RB_T), 0, p->stream, cnt, (const V2<T>*)psi, (T*)w.rho);
         NLF_HIP(hipGetLastError());
         NLF_TRY(potential(p, w.rho, w.pot));
-        hipLaunchKernelGGL((k_pot_phase<T>), grid, dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const T*)w.pot,
+        hipLaunchKernelGGL((k_pot_phase<T>), pgrid, dim3(RB_T), 0, p->stream, g, w.fl, Vext, (const T*)w.pot,
                            (V2<T>*)psi, t);
         NLF_HIP(hipGetLastError());
         pending += 0.5 * t;
