@@ -45,14 +45,16 @@ def train_model(X, T, hidden=128, epochs=3000, lr=2e-3, minibatch=0, seed=0):
     return m, hist
 
 
-def compare(model, instances, n, L, kernel, dim, coarse_n, tau=0.5, eps0=1e-10, prec=nlf.F64, mixed=False):
+def compare(model, instances, n, L, kernel, dim, coarse_n, tau=0.5, eps0=1e-10, prec=nlf.F64, mixed=False,
+            split=False):
     """Held-out solves from the Gaussian start (nlf_ground_state) and from the learned start
-    (nlf_ws_ground_state, Gaussian fallback judged by the one-step residual)."""
+    (nlf_ws_ground_state, Gaussian fallback judged by the one-step residual); split: the plan
+    evaluates the 3D potential by the split of Eq. '3.9'."""
     import torch
     betas = [d["beta"] for d in instances]
     gams = [d["gamma"] for d in instances]
     B = len(instances)
-    plan = nlf.Plan((n,) * dim, (L,) * dim, kernel, prec=prec, batch=B)
+    plan = nlf.Plan((n,) * dim, (L,) * dim, kernel, prec=prec, batch=B, split=split)
     kw = dict(tau=tau, eps0=eps0, max_iter=20000, mixed=mixed)
     model.ground_state(plan, betas[:1] * B, gams[:1] * B, coarse_n, **dict(kw, max_iter=1))   # warm-up
     torch.cuda.synchronize()
@@ -97,6 +99,8 @@ def main():
     ap.add_argument("--hidden", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=3000)
     ap.add_argument("--tau", type=float, default=0.5)
+    ap.add_argument("--split", action="store_true",
+                    help="held-out solves with the split evaluation of the 3D potential (Eq. '3.9')")
     args = ap.parse_args()
     import torch
     kernel = nlf.COULOMB3D if args.dim == 3 else nlf.COULOMB2D
@@ -120,6 +124,7 @@ def main():
     Yt = model.forward(Xt)
     rel = ((Yt - Tt).abs().amax(1) / Tt.abs().amax(1)).cpu().numpy()
     res = {"dim": args.dim, "n": args.n, "coarse": args.coarse, "train": args.train, "test": args.test,
+           "split": bool(args.split and args.dim == 3),
            "hidden": args.hidden, "epochs": args.epochs, "seconds_data": t_data, "seconds_train": t_train,
            "final_train_loss": float(hist[-1]), "heldout_coarse_rel_err_median": float(np.median(rel)),
            "heldout_coarse_rel_err_max": float(rel.max())}
@@ -127,7 +132,8 @@ def main():
     agg = {}
     for s in range(0, len(te), chunk):
         print(f"compare {s}/{len(te)}", file=sys.stderr, flush=True)
-        r = compare(model, te[s:s + chunk], args.n, args.L, kernel, args.dim, args.coarse, tau=args.tau)
+        r = compare(model, te[s:s + chunk], args.n, args.L, kernel, args.dim, args.coarse, tau=args.tau,
+                    split=args.split and args.dim == 3)
         for k, v in r.items():
             agg.setdefault(k, []).append(v)
     res.update({"compare_chunks": agg})
