@@ -13,6 +13,7 @@
 // The NUFFT sums these feed are those of Sec. 2.1, Eq. 'ifft'.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "nlf_internal.h"
 
@@ -579,11 +580,16 @@ static int launch_rows_cfg(nlf_plan* p, RowsArgs a, int batch) {
     if (a.n > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
     dim3 grid((a.nlines + a.lines_per_wg - 1) / a.lines_per_wg, batch);
     size_t lds = ((size_t)a.lines_per_wg * a.n + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // lines (+ twiddles)
+    // raised on first need; the check and the raise are one step, for plans driven from several threads
+    static std::mutex attr_mu;
     static size_t attr_bytes = 0;
-    if (lds > attr_bytes) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_bytes = lds;
+    {
+        std::lock_guard<std::mutex> lock(attr_mu);
+        if (lds > attr_bytes) {
+            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_bytes = lds;
+        }
     }
     hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
@@ -620,11 +626,16 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     a.ncb = a.bc2 ? (a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / C) : (int)(a.inner / C);
     dim3 grid(a.ncb, outer, batch);
     size_t lds = ((size_t)C * (a.n + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
+    // raised on first need; the check and the raise are one step, for plans driven from several threads
+    static std::mutex attr_mu;
     static size_t attr_bytes = 0;
-    if (lds > attr_bytes) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP, NT, E, TWL>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_bytes = lds;
+    {
+        std::lock_guard<std::mutex> lock(attr_mu);
+        if (lds > attr_bytes) {
+            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols<T, DIR, LP, SP, NT, E, TWL>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            attr_bytes = lds;
+        }
     }
     hipLaunchKernelGGL((k_fft_cols<T, DIR, LP, SP, NT, E, TWL>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
@@ -648,11 +659,16 @@ static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     a.ncb = (int)(a.inner / C);
     dim3 grid(a.ncb, 1, batch);
     size_t lds = ((size_t)C * (a.n + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
+    // raised on first need; the check and the raise are one step, for plans driven from several threads
+    static std::mutex attr_mu;
     static size_t attr_bytes = 0;
-    if (lds > attr_bytes) {
-        NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0<T, NT, E, TWL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-        attr_bytes = lds;
+    {
+        std::lock_guard<std::mutex> lock(attr_mu);
+        if (lds > attr_bytes) {
+            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0<T, NT, E, TWL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+            attr_bytes = lds;
+        }
     }
     hipLaunchKernelGGL((k_fft_conv0<T, NT, E, TWL>), grid, dim3(NT), lds, p->stream, a, cw);
     NLF_HIP(hipGetLastError());

@@ -48,7 +48,11 @@ int set_items(nlf_plan* p, int cap, bool bins) {
     if ((long long)items.size() > p->gitems_cap)
         return set_error(NLF_EINVAL, "work-item size %d below the allocated minimum", cap);
     NLF_HIP(hipStreamSynchronize(p->stream));   // no kernel of the plan may still read the items
-    if (!items.empty()) NLF_HIP(hipMemcpy(p->gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice));
+    if (!items.empty()) {
+        NLF_HIP(hipMemcpyAsync(p->gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice,
+                               p->stream));
+        NLF_HIP(hipStreamSynchronize(p->stream));   // `items` is released on return
+    }
     p->ngitems = (int)items.size();
     p->item_cap = cap;
     p->items_bins = bins ? 1 : 0;
@@ -143,9 +147,13 @@ static long double e1_plus_log(long double z) {
     return h * expl(-z) + logl(z);
 }
 
+// Every initialisation of device memory goes through the plan's stream: the stream may be a
+// non-blocking one, which the legacy default stream (where hipMemcpy and hipMemset run) does not
+// order against, so a plain copy or fill could land after the plan's first kernels.
 static int upload(nlf_plan* p, void** dst, const void* src, size_t bytes) {
     NLF_TRY(dev_alloc(p, dst, bytes));
-    NLF_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    NLF_HIP(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, p->stream));
+    NLF_HIP(hipStreamSynchronize(p->stream));   // the host table may be released on return
     return NLF_OK;
 }
 
@@ -222,7 +230,7 @@ static int build_split(nlf_plan* p, const nlf_box* box, int kernel, const nlf_op
         for (int i = 0; i < 3; ++i) fits = fits && 2 * band <= b->Mr[i] / 2;
         if (fits) {
             b->band = band;
-            NLF_HIP(hipMemset(b->grid_a, 0, (size_t)b->batch * b->G * elem_size(b->prec)));
+            NLF_HIP(hipMemsetAsync(b->grid_a, 0, (size_t)b->batch * b->G * elem_size(b->prec), b->stream));
         }
     }
     p->n_r = p->sub->n_r;
@@ -614,7 +622,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     p->t1_prec = (p->prec == NLF_F32 && (p->use_gather || p->gather_impl_ok)) ? NLF_F64 : p->prec;
     NLF_TRY(dev_alloc(p, &p->grid_a, (size_t)p->batch * p->G * es));
     NLF_TRY(dev_alloc(p, &p->grid_b, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
-    NLF_HIP(hipMemset(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec)));
+    NLF_HIP(hipMemsetAsync(p->grid_b, 0, (size_t)p->batch * p->G * elem_size(p->t1_prec), p->stream));
     NLF_TRY(dev_alloc(p, &p->cbuf, (size_t)p->batch * Mh * es));
     if (p->use_gather && p->dim == 3) NLF_TRY(dev_alloc(p, (void**)&p->iacc, (size_t)p->batch * Mh * 2 * sizeof(double)));
     for (int i = 0; i < p->dim; ++i) NLF_TRY(upload(p, (void**)&p->s[i], ss[i].data(), Mh * sizeof(double)));

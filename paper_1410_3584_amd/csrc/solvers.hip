@@ -615,7 +615,9 @@ static int ws_get(nlf_plan* p, SolverWs& w) {
     NLF_TRY(dev_alloc(p, &w.cw, B * N * ec));
     NLF_TRY(dev_alloc(p, &w.ph, B * N * ec));
     NLF_TRY(dev_alloc(p, &w.zf, (B + 1) / 2 * N * ec));
-    NLF_HIP(hipMemset(w.zf, 0, (B + 1) / 2 * N * ec));   // the unpaired half of an odd batch stays 0
+    // the unpaired half of an odd batch stays 0; cleared on the plan's stream, ahead of the solve's
+    // kernels (a fill on the legacy default stream is not ordered against a non-blocking stream)
+    NLF_HIP(hipMemsetAsync(w.zf, 0, (B + 1) / 2 * N * ec, p->stream));
     NLF_TRY(dev_alloc(p, (void**)&w.fl, B * sizeof(Fld)));
     NLF_TRY(dev_alloc(p, (void**)&w.part, 8 * B * MAXBLK * sizeof(double)));
     NLF_TRY(dev_alloc(p, (void**)&w.epart, B * MAXBLK * 4 * sizeof(double)));

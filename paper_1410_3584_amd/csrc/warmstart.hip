@@ -318,13 +318,14 @@ int nlf_ws_create(int n_in, int n_hidden, int n_out, unsigned long long seed, vo
         fill(0, n_in, n_hidden);
         fill(off_W2(m), n_hidden, n_hidden);
         fill(off_W3(m), n_hidden, n_out);
-        if (hipMemcpy(m->params, p.data(), m->np * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemset(m->m1, 0, m->np * sizeof(float)) != hipSuccess ||
-            hipMemset(m->m2, 0, m->np * sizeof(float)) != hipSuccess)
-            st = set_error(NLF_EHIP, "initialising the model failed");
+        // copies and fills on the model's stream (which may be non-blocking), completed before return
         float ms[16];
         for (int i = 0; i < 8; ++i) { ms[i] = m->mean[i]; ms[8 + i] = m->stdv[i]; }
-        if (st == NLF_OK && hipMemcpy(m->norm, ms, sizeof ms, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpyAsync(m->params, p.data(), m->np * sizeof(float), hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+            hipMemsetAsync(m->m1, 0, m->np * sizeof(float), m->stream) != hipSuccess ||
+            hipMemsetAsync(m->m2, 0, m->np * sizeof(float), m->stream) != hipSuccess ||
+            hipMemcpyAsync(m->norm, ms, sizeof ms, hipMemcpyHostToDevice, m->stream) != hipSuccess ||
+            hipStreamSynchronize(m->stream) != hipSuccess)
             st = set_error(NLF_EHIP, "initialising the model failed");
     }
     if (st != NLF_OK) {
@@ -355,8 +356,10 @@ int nlf_ws_num_params(const nlf_model* m, long long* count) {
 int nlf_ws_params(nlf_model* m, float* host_out, const float* host_in) {
     clear_error();
     if (!m) return set_error(NLF_EINVAL, "model must not be NULL");
-    if (host_in) NLF_HIP(hipMemcpy(m->params, host_in, m->np * sizeof(float), hipMemcpyHostToDevice));
-    if (host_out) NLF_HIP(hipMemcpy(host_out, m->params, m->np * sizeof(float), hipMemcpyDeviceToHost));
+    // ordered with the model's own work on its stream (which may be non-blocking)
+    if (host_in) NLF_HIP(hipMemcpyAsync(m->params, host_in, m->np * sizeof(float), hipMemcpyHostToDevice, m->stream));
+    if (host_out) NLF_HIP(hipMemcpyAsync(host_out, m->params, m->np * sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    NLF_HIP(hipStreamSynchronize(m->stream));
     return NLF_OK;
 }
 
@@ -371,7 +374,8 @@ int nlf_ws_set_standardisation(nlf_model* m, const float* mean, const float* std
         m->mean[i] = ms[i];
         m->stdv[i] = ms[8 + i];
     }
-    NLF_HIP(hipMemcpy(m->norm, ms, sizeof ms, hipMemcpyHostToDevice));
+    NLF_HIP(hipMemcpyAsync(m->norm, ms, sizeof ms, hipMemcpyHostToDevice, m->stream));
+    NLF_HIP(hipStreamSynchronize(m->stream));
     return NLF_OK;
 }
 

@@ -214,7 +214,9 @@ def test_gs_batched_workload_full():
     """Batched 2D ground-state workload at full size: 64 instances on [-16,16]^2 with grids drawn
     from {64^2, 128^2, 256^2}, beta ~ U[10,1000], gamma ~ U[0.5,2], Coulomb kernel, FP32 bulk and
     FP64 polish, autotuned spreading, solved concurrently (one plan and stream per size).  Every
-    field reaches the 1e-10 residual; sampled fields equal their own FP64 solve."""
+    field reaches the 1e-10 residual; every field of the 64^2 and 128^2 groups and a sampled one
+    of the 256^2 group equal their own FP64 solve (a field whose FP64 stage stopped early keeps
+    an FP32-quality energy, off by 1e-8 to 1e-6)."""
     print("[gs batched workload]", flush=True)
     inst = inputs.ground_state_batch_2d(seed=3, count=64)
     groups = {}
@@ -235,12 +237,14 @@ def test_gs_batched_workload_full():
     assert max(s["residual"] for a in stats for s in a) <= 1e-10
     rng = np.random.default_rng(0)
     for i, k in enumerate(keys):
-        j = int(rng.integers(0, len(groups[k])))
+        js = range(len(groups[k])) if k <= 128 else [int(rng.integers(0, len(groups[k])))]
         single = nlf.Plan((k, k), (16.0, 16.0), nlf.COULOMB2D)
-        psi, st, s1 = single.ground_state(betas[i][j], gams[i][j], tau=0.25, eps0=1e-10, max_iter=5000)
-        assert s1 == nlf.OK
-        assert abs(stats[i][j]["E"] - st[0]["E"]) <= 1e-9 * abs(st[0]["E"]), (k, j)
-        assert rel_err(outs[i][j].cpu().numpy().astype(np.float64), psi.cpu().numpy()) < 1e-6
+        for j in js:
+            psi, st, s1 = single.ground_state(betas[i][j], gams[i][j], tau=0.25, eps0=1e-10, max_iter=5000)
+            assert s1 == nlf.OK
+            assert stats[i][j]["iters"] > stats[i][j]["iters_fp32"] + 1, (k, j, stats[i][j])
+            assert abs(stats[i][j]["E"] - st[0]["E"]) <= 1e-9 * abs(st[0]["E"]), (k, j, stats[i][j])
+            assert rel_err(outs[i][j].cpu().numpy().astype(np.float64), psi.cpu().numpy()) < 1e-6
 
 
 # ---- dynamics ---------------------------------------------------------------------------------
