@@ -197,6 +197,9 @@ struct RowsArgs {
     int accum;             // STORE_U: add to u instead of overwriting it
     int band;              // > 0: only the cells |f| < band of a line are nonzero / needed (the
                            // ball of a split): LOAD_GRID reads only those, STORE_GRID writes only those
+    int half;              // > 0: a grid line holds the first `half` (> n/2) outputs of a transform of
+                           // real data, line pitch `half`: STORE_GRID writes those, LOAD_GRID
+                           // rebuilds the rest from the Hermitian symmetry v[n - c] = conj v[c]
     // 2D Laplace: u += m0 u11 - m1 . u12 (Sec. 2.2, Eqs. 'phi1_exct', 'phi12_ext')
     int add_u1;
     const double* mom;     // [batch][4]: m0, m1x, m1y
@@ -327,7 +330,13 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
                 double fac;
                 int j0, j1;
                 const long long gl = grid_line(l, &fac, &j0, &j1);
-                if (!a.band || is_data_row(c, 2 * a.band, n)) v[u] = grid[gl * n + c];
+                if (a.half) {
+                    const bool lo = c <= (n >> 1);
+                    const V2<T> w = grid[gl * a.half + (lo ? c : n - c)];
+                    v[u] = lo ? w : mk<T>(w.x, -w.y);
+                } else if (!a.band || is_data_row(c, 2 * a.band, n)) {
+                    v[u] = grid[gl * n + c];
+                }
             }
         }
 #pragma unroll
@@ -345,7 +354,15 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     lds_fft<T, DIR, NT, E, TWL>(buf, pitch, n, a.lg, nl, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
 
     // ---- store
-    if (STORE == STORE_GRID) {
+    if (STORE == STORE_GRID && a.half) {
+        for (int idx = threadIdx.x; idx < nl * a.half; idx += NT) {
+            int l = idx / a.half, c = idx - l * a.half;
+            double fac;
+            int j0, j1;
+            long long gl = grid_line(l, &fac, &j0, &j1);
+            grid[gl * a.half + c] = buf[l * pitch + c];
+        }
+    } else if (STORE == STORE_GRID) {
         for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
             int l = idx / n, c = idx - l * n;
             double fac;
@@ -485,6 +502,7 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
 // only: the full Mr0-row spectrum never goes to memory.
 struct ConvW {
     int Mr0, Mr1, Mr2;
+    int pitch2;            // stored columns of the innermost axis (its first pitch2 frequencies)
     double dk0, dk1, dk2, inva;
 };
 
@@ -524,7 +542,7 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
         const long long col = col0 + c;
-        const int c1 = (int)(col / cw.Mr2), c2 = (int)(col - (long long)c1 * cw.Mr2);
+        const int c1 = (int)(col / cw.pitch2), c2 = (int)(col - (long long)c1 * cw.pitch2);
         const double k0 = (r < cw.Mr0 / 2 ? r : r - cw.Mr0) * cw.dk0;
         const double k1 = (c1 < cw.Mr1 / 2 ? c1 : c1 - cw.Mr1) * cw.dk1;
         const double k2 = (c2 < cw.Mr2 / 2 ? c2 : c2 - cw.Mr2) * cw.dk2;
@@ -678,9 +696,13 @@ static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
 // I1 of a split (Eq. '3.9'), 3D: the cyclic convolution of the zero-padded density with the lattice
 // transform of w, u += (1/G) IFFT(w . FFT(pad rho)), truncated to the data grid.  The plan's pre-
 // and post-correction tables are ones, so the row and axis-1 passes are the plain padded FFT; the
-// axis-0 passes and the multiply are one fused kernel.
+// axis-0 passes and the multiply are one fused kernel.  rho is real and w real and even, so the
+// spectrum is Hermitian and, after the inverse axis-0 and axis-1 passes, every line along axis 2 is
+// Hermitian in its own frequency: only the first H = Mr2/2 + 16 frequencies of axis 2 are kept
+// (H a multiple of the column blocks), about half the data of the axis-1 and axis-0 passes.
 template <typename T>
 static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
+    const int H = std::min(p->Mr[2], p->Mr[2] / 2 + 16);
     RowsArgs r{};
     r.grid = p->grid_a;
     r.gstride = p->G;
@@ -694,16 +716,17 @@ static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
     r.dec2 = p->dec[2];
     r.tw = p->tw_big[2];
     r.nlines = p->n[0] * p->n[1];
+    r.half = H;
     NLF_TRY((launch_rows<T, -1, LOAD_RHO, STORE_GRID>(p, r, p->batch)));
     ColsArgs c{};
-    c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = p->Mr[2];
+    c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = H;
     c.outer_mapped = 1; c.outer_nd = p->n[0]; c.outer_Mr = p->Mr[0];
     c.nd = p->n[1]; c.tw = p->tw_big[1];
     NLF_TRY((launch_cols<T, -1, true, false>(p, c, p->n[0], p->batch)));
     ColsArgs c0{};
-    c0.grid = p->grid_a; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * p->Mr[2];
+    c0.grid = p->grid_a; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * H;
     c0.nd = p->n[0]; c0.tw = p->tw_big[0];
-    ConvW cw{p->Mr[0], p->Mr[1], p->Mr[2], 0, 0, 0, 1.0 / p->split_a};
+    ConvW cw{p->Mr[0], p->Mr[1], p->Mr[2], H, 0, 0, 0, 1.0 / p->split_a};
     cw.dk0 = 2.0 * 3.14159265358979323846 / (p->Mr[0] * p->h[0]);
     cw.dk1 = 2.0 * 3.14159265358979323846 / (p->Mr[1] * p->h[1]);
     cw.dk2 = 2.0 * 3.14159265358979323846 / (p->Mr[2] * p->h[2]);
