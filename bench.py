@@ -156,6 +156,28 @@ def load_traffic(kernel_stage):
     return None if v is None else float(v)
 
 
+def batched_evals(torch, nlf, n, L, rho, steps, warmup, batch=8):
+    """The same 2D evaluations with `batch` fields per call (plans with opts.batch): potential
+    evals/s (fields/s) of the K2/K3 alternation in FP64 and FP32, beside the single-field headline."""
+    out = {"batch": batch, "unit": "potential evals/s"}
+    for prec, dt, key in ((nlf.F64, torch.float64, "f64"), (nlf.F32, torch.float32, "f32")):
+        r = torch.tensor(np.stack([rho] * batch), dtype=dt, device="cuda").contiguous()
+        u = torch.empty_like(r)
+        pk = [nlf.Plan(n, L, k, prec=prec, batch=batch) for k in (nlf.COULOMB2D, nlf.LAPLACE2D)]
+        for _ in range(warmup):
+            for p in pk:
+                p.potential(r, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for p in pk:
+                p.potential(r, u)
+        torch.cuda.synchronize()
+        out[key] = 2 * steps * batch / (time.perf_counter() - t0)
+        del pk
+    return out
+
+
 def ground_states_per_s(torch, nlf, inputs):
     """Second half of the metric: 64 batched 2D ground states (grids drawn from 64^2/128^2/256^2 on
     [-16,16]^2, beta ~ U[10,1000], gamma ~ U[0.5,2], Coulomb 2D), gradient flow to
@@ -313,6 +335,7 @@ def main():
         step(1)
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
+    batched = batched_evals(torch, nlf, n, L, rho, args.steps, args.warmup)
 
     # ---- live per-stage timing (HIP events on the plan's stream) for the roofline ----
     stage_avg = {}
@@ -373,6 +396,7 @@ def main():
                                "kernels 1/(2 pi|x|) and -ln|x|/(2 pi) alternating, 512x1024 polar nodes, w=24",
                    "grid": [512, 512], "nodes": 524288, "msp_f64": 12, "msp_f32": 7},
         "fp32": {"value": 2 * args.steps / t32, "unit": "potential evals/s", "msp": 7},
+        "batched": batched,
         "parity_rel_err": parity,
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage_avg.items()},
         "roofline": roof,
