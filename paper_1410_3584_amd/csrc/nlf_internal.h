@@ -53,6 +53,17 @@ struct GItem {
 };
 constexpr int kMChunk = 128;
 constexpr int kMItem = 1024;
+
+// A launch's work list split over the 8 XCDs.  Hardware workgroup ids go round-robin over the XCDs,
+// so XCD x runs the workgroups b with b mod 8 = x; it takes the consecutive entries [s[x], s[x+1])
+// of the list (neighbouring bins and tiles share its L2), the cuts placed at equal estimated cost
+// (the polar nodes crowd the low frequencies, so equal entry counts leave some XCDs with far more
+// work).  The launch has 8 per workgroups, per = the longest range.
+struct XcdSplit {
+    int s[9];
+    int per;
+};
+XcdSplit xcd_split(const std::vector<long long>& cost);
 // neighbour-bin gather: most neighbour bins a tile may read (5 x 9 x 9 at msp 16 in 3D)
 constexpr int kMaxNbrBins = 512;
 
@@ -101,12 +112,14 @@ struct nlf_plan {
     int* perm = nullptr;        // sorted node -> canonical half index
     nlf::Chunk* chunks = nullptr;
     int nchunks = 0;
+    nlf::XcdSplit chunk_split{};   // chunks over the XCDs (2D interpolation)
     // output-driven spreading: per gather tile, the sorted nodes whose stencil overlaps it
     int gtile[3] = {1, 1, 1};
     int use_gather = 0;
     int* gcand = nullptr;
     nlf::GItem* gitems = nullptr;
     int ngitems = 0;
+    nlf::XcdSplit item_split{};    // gather work items over the XCDs
     double* iacc = nullptr;     // [batch][Mh] complex FP64: tile-gathered interpolation sums
     // spreading work decomposition (nlf_plan_set_spread / nlf_plan_autotune)
     int spread_mode = 0;        // NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER

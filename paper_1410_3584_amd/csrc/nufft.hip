@@ -75,6 +75,8 @@ struct NodeArgs {
     const Chunk* chunks;
     int nchunks;
     GaussConst gc;
+    XcdSplit csplit;        // chunks over the XCDs (2D interpolation)
+    XcdSplit isplit;        // gather work items over the XCDs (3D interpolation, spreading)
 };
 
 struct EpiArgs {
@@ -96,6 +98,11 @@ __device__ __forceinline__ int chunk_id(int nchunks) {
     int b = blockIdx.x;
     int per = (nchunks + 7) >> 3;
     return (b & 7) * per + (b >> 3);
+}
+// entry of a cost-balanced split taken by this workgroup, or -1 (its XCD's range is shorter)
+__device__ __forceinline__ int split_id(const XcdSplit& xs) {
+    const int x = blockIdx.x & 7, id = xs.s[x] + (blockIdx.x >> 3);
+    return id < xs.s[x + 1] ? id : -1;
 }
 
 template <typename T>
@@ -472,8 +479,8 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
     static_assert(KC % (4 * NW) == 0 && (KC / NW) % 8 == 0, "whole pairs of MFMA steps per wave");
     static_assert(2 * KC * 16 >= NW * 4 * 64, "wave partials fit S");
     __shared__ __align__(16) double S[2 * KC * 16];
-    const int iid = chunk_id(nitems);
-    if (iid >= nitems) return;
+    const int iid = split_id(na.isplit);
+    if (iid < 0) return;
     const GItem it = items[iid];
     const int b = blockIdx.y;
     const int t = threadIdx.x;
@@ -630,8 +637,8 @@ __global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ g
         const long long e = min(zero16, (wg + 1) * per);
         for (long long i = wg * per + threadIdx.x; i < e; i += 256) zero[i] = make_double2(0.0, 0.0);
     }
-    const int cid = chunk_id(na.nchunks);
-    if (cid >= na.nchunks) return;
+    const int cid = split_id(na.csplit);
+    if (cid < 0) return;
     const Chunk ch = na.chunks[cid];
     const int b = blockIdx.y;
     const int t = threadIdx.x;
@@ -762,8 +769,8 @@ __global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict
     __shared__ double W1T[16][kMChunk];   // B operand, one row per tile column j
     __shared__ double W0T[8][kMChunk];    // w0 per tile row x
     __shared__ int nodes[kMChunk];
-    const int iid = chunk_id(nitems);
-    if (iid >= nitems) return;
+    const int iid = split_id(na.isplit);
+    if (iid < 0) return;
     const GItem it = items[iid];
     const int b = blockIdx.y;
     const int t = threadIdx.x;
@@ -920,6 +927,8 @@ static NodeArgs node_args(const nlf_plan* p) {
     na.chunks = p->chunks;
     na.nchunks = p->nchunks;
     na.gc = p->gc;
+    na.csplit = p->chunk_split;
+    na.isplit = p->item_split;
     return na;
 }
 
@@ -934,7 +943,7 @@ template <typename T, int MSP>
 static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
     NodeArgs na = node_args(p);
     if (p->dim == 2) {
-        dim3 grid(grid_chunks(p), p->batch);
+        dim3 grid(8 * p->chunk_split.per, p->batch);
         const double qq4 = exp(-32.0 * p->gc.alpha);
         const size_t bbytes = (size_t)p->batch * p->G * elem_size(p->t1_prec);   // a multiple of 16
         hipLaunchKernelGGL((k_binterp2<T, MSP>), grid, dim3(256), 0, p->stream,
@@ -947,7 +956,7 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
     // items; with neighbour-bin items in use it takes the plane-streamed kernel)
     if (p->use_gather && !p->items_bins) {
         NLF_TRY(fill_zero(p, p->iacc, (size_t)p->batch * p->Mh * 2 * sizeof(double)));
-        dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
+        dim3 ggrid(8 * p->item_split.per, p->batch);
         const double qq = exp(-2.0 * p->gc.alpha);
         const V2<T>* g = reinterpret_cast<const V2<T>*>(p->grid_a);
         if (p->dim == 2)
@@ -975,7 +984,7 @@ static int gather_spread_t(nlf_plan* p) {
     NodeArgs na = node_args(p);
     V2<T>* g = reinterpret_cast<V2<T>*>(p->grid_b);
     const V2<T>* c = reinterpret_cast<const V2<T>*>(p->cbuf);
-    dim3 ggrid(((p->ngitems + 7) / 8) * 8, p->batch);
+    dim3 ggrid(8 * p->item_split.per, p->batch);
     const double qq = exp(-2.0 * p->gc.alpha);
     BinArgs ba{};
     ba.bin_off = p->bin_off;

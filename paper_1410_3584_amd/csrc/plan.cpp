@@ -24,6 +24,28 @@ void clear_error() { g_err[0] = 0; }
 
 size_t elem_size(int prec) { return prec == NLF_F64 ? 16 : 8; }
 
+XcdSplit xcd_split(const std::vector<long long>& cost) {
+    XcdSplit xs{};
+    const int n = (int)cost.size();
+    long long total = 0;
+    for (long long c : cost) total += c;
+    long long acc = 0;
+    int x = 1;
+    for (int i = 0; i < n && x < 8; ++i) {
+        acc += cost[i];
+        while (x < 8 && acc * 8 >= total * x) xs.s[x++] = i + 1;
+    }
+    while (x <= 8) xs.s[x++] = n;
+    xs.per = 1;
+    for (int k = 0; k < 8; ++k) xs.per = std::max(xs.per, xs.s[k + 1] - xs.s[k]);
+    return xs;
+}
+
+// Estimated cost of a gather work item or an interpolation chunk: its nodes plus a fixed part (the
+// tile's write-back, the window's staging).
+constexpr long long kItemFixed = 64;
+constexpr long long kChunkFixed = 64;
+
 // Work items of the gather kernels: the candidates of each tile cut into pieces of <= cap.
 int set_items(nlf_plan* p, int cap, bool bins) {
     std::vector<GItem> items;
@@ -55,6 +77,11 @@ int set_items(nlf_plan* p, int cap, bool bins) {
     }
     p->ngitems = (int)items.size();
     p->item_cap = cap;
+    {
+        std::vector<long long> cost(items.size());
+        for (size_t i = 0; i < items.size(); ++i) cost[i] = items[i].count + kItemFixed;
+        p->item_split = xcd_split(cost);
+    }
     p->items_bins = bins ? 1 : 0;
     return NLF_OK;
 }
@@ -436,6 +463,11 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         }
     }
     p->nchunks = (int)chunks.size();
+    {
+        std::vector<long long> cost(chunks.size());
+        for (size_t i = 0; i < chunks.size(); ++i) cost[i] = chunks[i].count + kChunkFixed;
+        p->chunk_split = xcd_split(cost);
+    }
 
     // ---- candidate lists for the output-driven spreading ------------------------------------
     // A node at l0 touches cells (l0 + p) mod Mr, p = -msp+1..msp, along each axis; list it under
