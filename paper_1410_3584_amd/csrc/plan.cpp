@@ -45,6 +45,14 @@ XcdSplit xcd_split(const std::vector<long long>& cost) {
 // tile's write-back, the window's staging).
 constexpr long long kItemFixed = 64;
 constexpr long long kChunkFixed = 64;
+// Within each XCD's range the entries with the most nodes go first, so that the range does not end
+// on a long one (512^2 FP64: interpolation 42.8 -> 39.6 us, spreading 57.3 -> 55.7 us).
+template <class E>
+static void heavy_first(std::vector<E>& v, const XcdSplit& xs) {
+    for (int x = 0; x < 8; ++x)
+        std::stable_sort(v.begin() + xs.s[x], v.begin() + xs.s[x + 1],
+                         [](const E& a, const E& b) { return a.count > b.count; });
+}
 
 // Work items of the gather kernels: the candidates of each tile cut into pieces of <= cap.
 int set_items(nlf_plan* p, int cap, bool bins) {
@@ -69,6 +77,13 @@ int set_items(nlf_plan* p, int cap, bool bins) {
     }
     if ((long long)items.size() > p->gitems_cap)
         return set_error(NLF_EINVAL, "work-item size %d below the allocated minimum", cap);
+    XcdSplit xs;
+    {
+        std::vector<long long> cost(items.size());
+        for (size_t i = 0; i < items.size(); ++i) cost[i] = items[i].count + kItemFixed;
+        xs = xcd_split(cost);
+        heavy_first(items, xs);
+    }
     NLF_HIP(hipStreamSynchronize(p->stream));   // no kernel of the plan may still read the items
     if (!items.empty()) {
         NLF_HIP(hipMemcpyAsync(p->gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice,
@@ -76,12 +91,8 @@ int set_items(nlf_plan* p, int cap, bool bins) {
         NLF_HIP(hipStreamSynchronize(p->stream));   // `items` is released on return
     }
     p->ngitems = (int)items.size();
+    p->item_split = xs;
     p->item_cap = cap;
-    {
-        std::vector<long long> cost(items.size());
-        for (size_t i = 0; i < items.size(); ++i) cost[i] = items[i].count + kItemFixed;
-        p->item_split = xcd_split(cost);
-    }
     p->items_bins = bins ? 1 : 0;
     return NLF_OK;
 }
@@ -467,6 +478,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         std::vector<long long> cost(chunks.size());
         for (size_t i = 0; i < chunks.size(); ++i) cost[i] = chunks[i].count + kChunkFixed;
         p->chunk_split = xcd_split(cost);
+        heavy_first(chunks, p->chunk_split);
     }
 
     // ---- candidate lists for the output-driven spreading ------------------------------------
