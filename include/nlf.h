@@ -25,9 +25,11 @@
  *    the duration of the call's stream work; the library never frees caller memory.  Plans own
  *    their workspaces (allocated in nlf_plan_create, freed in nlf_plan_destroy).
  *  * Streams: all device work of a plan is enqueued on the HIP stream given at plan creation
- *    (NULL = the default stream).  Calls return when the work is enqueued unless stated
+ *    (NULL = the default stream), the one-time work too (table uploads, buffer clears), so a
+ *    non-blocking stream is safe.  Calls return when the work is enqueued unless stated
  *    otherwise; the solvers synchronise the stream to read convergence flags.
- *  * Concurrency: a plan is not re-entrant; use one plan per stream.
+ *  * Concurrency: a plan is not re-entrant; use one plan per stream.  Different plans may be
+ *    driven from different host threads at the same time.
  *  * Errors: every call returns an int status; 0 is success, negative values are errors.
  *    nlf_last_error() returns a message for the calling thread's last error.  No C++
  *    exception crosses this boundary.
