@@ -261,6 +261,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ground-states", action="store_true")
     ap.add_argument("--no-dynamics-3d", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -335,7 +336,7 @@ def main():
         step(1)
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
-    batched = batched_evals(torch, nlf, n, L, rho, args.steps, args.warmup)
+    batched = None if args.no_batched else batched_evals(torch, nlf, n, L, rho, args.steps, args.warmup)
 
     # ---- live per-stage timing (HIP events on the plan's stream) for the roofline ----
     stage_avg = {}

@@ -610,12 +610,24 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
             p->gitems_cap = most;
             NLF_TRY(dev_alloc(p, (void**)&p->gitems, (size_t)p->gitems_cap * sizeof(GItem)));
         }
-        // default: the explicit lists with 512-candidate items for the wide FP64 stencils and 256
-        // for narrower ones (the fastest on the 2D workloads measured; nlf_plan_autotune picks
-        // per plan); neighbour bins with 1024-candidate items where the lists were not built
+        // default: the explicit lists with the largest items (1024 or 512 candidates) that still
+        // leave 4096 work items per field, else 256-candidate items (the fastest on the 512^2
+        // workloads measured: 1024 for FP64, msp 12, and 512 for FP32, msp 7; 256 on the small
+        // solver grids; nlf_plan_autotune picks per plan); neighbour bins with 1024-candidate
+        // items where the lists were not built
         if (p->use_gather) {
             p->spread_mode = NLF_SPREAD_GATHER;
-            NLF_TRY(set_items(p, p->msp >= 10 ? 512 : 256, false));
+            int cap = 256;
+            for (int c : {1024, 512}) {
+                long long nit = 0;
+                for (size_t t = 0; t + 1 < p->gtile_off.size(); ++t)
+                    nit += (p->gtile_off[t + 1] - p->gtile_off[t] + c - 1) / c;
+                if (nit >= 4096) {
+                    cap = c;
+                    break;
+                }
+            }
+            NLF_TRY(set_items(p, cap, false));
         } else if (p->gather_impl_ok) {
             p->spread_mode = NLF_SPREAD_BINS;
             NLF_TRY(set_items(p, 1024, true));
