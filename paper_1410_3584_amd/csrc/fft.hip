@@ -50,7 +50,7 @@ __device__ __forceinline__ int dmap(int j, int nd, int Mr) {
 }
 __device__ __forceinline__ bool is_data_row(int r, int nd, int Mr) { return r < nd / 2 || r >= Mr - nd / 2; }
 
-// In-place multi-line Stockham FFT of nl lines of length n = 2^lg held in buf[line*pitch + i].
+// In-place multi-line Stockham FFT of nl lines of length n = 2^lg held in buf[line*pitch + lpad<HALF>(i)].
 // tw[t] = exp(-2 pi i t / n).  DIR = -1 forward, +1 inverse (unnormalised).  Mixed radix: one radix-2 or radix-4 pass first when lg is not a multiple of 3, then radix-8
 // passes, each a read of the whole buffer into registers and a write back (fewer LDS round trips
 // than radix 4: 512 points take 3 passes instead of 5).  Pass with radix R over the index range
@@ -99,7 +99,19 @@ __device__ __forceinline__ void dft8(V2<T> (&a)[8]) {
     a[7] = csub<T>(e3, o3);
 }
 
-template <typename T, int DIR, int NT, int E, int R, bool HALF>
+// LDS position of element e of a line, PAD: one padding slot after every 8 elements.  A radix-8
+// pass writes 8 consecutive outputs per thread (the first pass) or runs of 8 (the second);
+// unpadded, the lanes of a wave then hit the same few banks (16-byte elements 128 bytes apart),
+// padded they spread.  The column kernels pad lines of up to 512 points (256^3: fused axis-0
+// kernel 928 -> 821 us, axis-1 passes 218/213 -> 202/194 us), which is exactly when their twiddles
+// are staged in LDS (TWL); the 1024-point columns of the 2D grids are not padded (padded, a 512^2
+// evaluation took 4.5% longer), nor are the row kernels (their 512-point lines took 209 -> 226 us
+// padded: the larger LDS footprint costs a workgroup per CU).
+template <bool PAD>
+__device__ __forceinline__ int lpad(int e) { return PAD ? e + (e >> 3) : e; }
+__host__ __device__ __forceinline__ int lds_line(int n, bool pad) { return pad ? n + (n >> 3) : n; }
+
+template <typename T, int DIR, int NT, int E, int R, bool HALF, bool PAD>
 __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, int p, const V2<T>* __restrict__ tw) {
     constexpr int RB = (E + R * NT - 1) / (R * NT);   // butterflies per thread
     const int q = n / R;
@@ -115,7 +127,7 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
             const int k = i & (p - 1);
             const V2<T>* x = buf + line * pitch;
 #pragma unroll
-            for (int m = 0; m < R; ++m) y[r][m] = x[i + m * q];
+            for (int m = 0; m < R; ++m) y[r][m] = x[lpad<PAD>(i + m * q)];
             if (p > 1) {
 #pragma unroll
                 for (int m = 1; m < R; ++m) {
@@ -153,25 +165,25 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
             const int j = (i - k) * R + k;
             V2<T>* x = buf + line * pitch;
 #pragma unroll
-            for (int m = 0; m < R; ++m) x[j + m * p] = y[r][m];
+            for (int m = 0; m < R; ++m) x[lpad<PAD>(j + m * p)] = y[r][m];
         }
     }
     __syncthreads();
 }
 
 // HALF: tw holds w^t for t < n/2 only (the LDS copy); otherwise the full table
-template <typename T, int DIR, int NT, int E, bool HALF = false>
+template <typename T, int DIR, int NT, int E, bool HALF = false, bool PAD = HALF>
 __device__ void lds_fft(V2<T>* buf, int pitch, int n, int lg, int nl, const V2<T>* __restrict__ tw) {
     int p = 1;
     if (lg % 3 == 1) {
-        fft_pass<T, DIR, NT, E, 2, HALF>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 2, HALF, PAD>(buf, pitch, n, nl, p, tw);
         p = 2;
     } else if (lg % 3 == 2) {
-        fft_pass<T, DIR, NT, E, 4, HALF>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 4, HALF, PAD>(buf, pitch, n, nl, p, tw);
         p = 4;
     }
     while (p < n) {
-        fft_pass<T, DIR, NT, E, 8, HALF>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 8, HALF, PAD>(buf, pitch, n, nl, p, tw);
         p *= 8;
     }
 }
@@ -229,7 +241,7 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
     constexpr int NT = RowCfg::NT;
     const int n = a.n;
-    const int pitch = n;
+    const int pitch = n;   // rows are not padded (see lpad)
     const int b = blockIdx.y;
     const int line0 = blockIdx.x * a.lines_per_wg;
     const int nl = min(a.lines_per_wg, a.nlines - line0);
@@ -351,7 +363,7 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
         if (TWL && i < (n >> 1)) twl[i] = tv[u];
     }
     __syncthreads();
-    lds_fft<T, DIR, NT, E, TWL>(buf, pitch, n, a.lg, nl, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
+    lds_fft<T, DIR, NT, E, TWL, false>(buf, pitch, n, a.lg, nl, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
 
     // ---- store
     if (STORE == STORE_GRID && a.half) {
@@ -441,7 +453,7 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
     const int n = a.n, C = a.C;
-    const int pitch = n + 1;
+    const int pitch = lds_line(n, TWL) + 1;
     if (a.mom && blockIdx.x == 0 && blockIdx.y == 0) {   // uniform over the workgroup
         __shared__ double red16[16];
         const double* part = a.mom_part + (long long)blockIdx.z * a.mom_nblk * 3;
@@ -484,7 +496,7 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
-        if (idx < n * C) buf[(idx % C) * pitch + idx / C] = v[u];
+        if (idx < n * C) buf[(idx % C) * pitch + lpad<TWL>(idx / C)] = v[u];
         if (TWL && idx < (n >> 1)) twl[idx] = tv[u];
     }
     __syncthreads();
@@ -492,7 +504,7 @@ __global__ void __launch_bounds__(NT) k_fft_cols(ColsArgs a) {
     const int nds = a.nd_store > 0 ? a.nd_store : a.nd;
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
-        if (!SPRUNE || is_data_row(r, nds, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
+        if (!SPRUNE || is_data_row(r, nds, n)) base[(long long)r * a.inner + c] = buf[c * pitch + lpad<TWL>(r)];
     }
 }
 
@@ -511,7 +523,7 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
     const int n = a.n, C = a.C;
-    const int pitch = n + 1;
+    const int pitch = lds_line(n, TWL) + 1;
     int cb = blockIdx.x;
     const int nb = gridDim.x;
     if ((nb & 7) == 0) cb = (cb & 7) * (nb >> 3) + (cb >> 3);
@@ -533,7 +545,7 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
-        if (idx < n * C) buf[(idx % C) * pitch + idx / C] = v[u];
+        if (idx < n * C) buf[(idx % C) * pitch + lpad<TWL>(idx / C)] = v[u];
         if (TWL && idx < (n >> 1)) twl[idx] = tv[u];
     }
     __syncthreads();
@@ -548,17 +560,17 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
         const double k2 = (c2 < cw.Mr2 / 2 ? c2 : c2 - cw.Mr2) * cw.dk2;
         const double kk = k0 * k0 + k1 * k1 + k2 * k2;
         const double w = kk > 0.0 ? -expm1(-kk * cw.inva) / kk : cw.inva;
-        V2<T> v = buf[c * pitch + r];
+        V2<T> v = buf[c * pitch + lpad<TWL>(r)];
         v.x = (T)((double)v.x * w);
         v.y = (T)((double)v.y * w);
-        buf[c * pitch + r] = v;
+        buf[c * pitch + lpad<TWL>(r)] = v;
     }
     __syncthreads();
     lds_fft<T, 1, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     __syncthreads();
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
         int r = idx / C, c = idx - r * C;
-        if (is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + r];
+        if (is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + lpad<TWL>(r)];
     }
 }
 
@@ -643,7 +655,7 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
         return set_error(NLF_EINVAL, "column band %d/%d does not fit the grid", a.bc1, a.bc2);
     a.ncb = a.bc2 ? (a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / C) : (int)(a.inner / C);
     dim3 grid(a.ncb, outer, batch);
-    size_t lds = ((size_t)C * (a.n + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
+    size_t lds = ((size_t)C * (lds_line(a.n, TWL) + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
     // raised on first need; the check and the raise are one step, for plans driven from several threads
     static std::mutex attr_mu;
     static size_t attr_bytes = 0;
@@ -676,7 +688,7 @@ static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     a.C = C;
     a.ncb = (int)(a.inner / C);
     dim3 grid(a.ncb, 1, batch);
-    size_t lds = ((size_t)C * (a.n + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
+    size_t lds = ((size_t)C * (lds_line(a.n, TWL) + 1) + (TWL ? a.n / 2 : 0)) * sizeof(V2<T>);   // columns (+ twiddles)
     // raised on first need; the check and the raise are one step, for plans driven from several threads
     static std::mutex attr_mu;
     static size_t attr_bytes = 0;

@@ -215,13 +215,15 @@ def test_single_point_density():
 
 
 def test_repeat_calls_identical_structure():
-    """Two calls on the same plan agree to rounding (the spread grid is cleared between calls)."""
+    """Two calls on the same plan agree to rounding (the spread grid is cleared between calls: a
+    stale grid would double the second result).  The FP64 atomics of the spreading add in no fixed
+    order, so the two calls may differ by some tens of ulps (1.06e-14 seen)."""
     n, L = (64, 64), (8.0, 8.0)
     rho = to_dev(_case_density(n, L, 9), 0)
     plan = nlf.Plan(n, L, nlf.COULOMB2D)
     a = plan.potential(rho).cpu().numpy()
     b = plan.potential(rho).cpu().numpy()
-    assert rel_err(a, b) <= 1e-14
+    assert rel_err(a, b) <= 1e-13
 
 
 def test_invalid_arguments_rejected():
