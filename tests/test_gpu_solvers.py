@@ -210,6 +210,43 @@ def test_gs_batch_over_plans_of_uneven_size(graph):
             assert abs(stats[i][j]["E"] - st[0]["E"]) < 1e-10
 
 
+def test_plans_on_nonblocking_streams_while_the_device_is_busy():
+    """Plans built and used on non-blocking streams (torch's are) while the default stream is busy
+    with a large matrix product.  Every one-time initialisation goes through the plan's own stream
+    (table uploads, grid clears, the solver workspace's clears, the FP64 twin plan of the mixed
+    schedule), so results equal those of plans on the default stream.  A clear left on the legacy
+    default stream would wait for the product and land after the plan's first kernels."""
+    print("[non-blocking streams]", flush=True)
+    n, L = (128, 128), (16.0, 16.0)
+    rho, _ = inputs.density_2d_bumps(n, L, seed=5, n_bumps=4)
+    r = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    busy = torch.randn(4096, 4096, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ref = nlf.Plan(n, L, nlf.COULOMB2D).potential(r).cpu().numpy()
+    for _ in range(3):
+        s = torch.cuda.Stream()
+        _ = busy @ busy
+        plan = nlf.Plan(n, L, nlf.COULOMB2D, stream=s.cuda_stream)
+        u = plan.potential(r)
+        s.synchronize()
+        assert rel_err(u.cpu().numpy(), ref) <= 1e-13
+    betas, gams = [50.0, 200.0, 400.0], [(1.0, 1.2), (1.0, 0.8), (1.0, 1.5)]
+    want = []
+    for b, g in zip(betas, gams):
+        _, st, status = nlf.Plan((64, 64), L, nlf.COULOMB2D).ground_state(b, g, tau=0.25, eps0=1e-10)
+        assert status == nlf.OK
+        want.append(st[0]["E"])
+    s = torch.cuda.Stream()
+    _ = busy @ busy
+    p = nlf.Plan((64, 64), L, nlf.COULOMB2D, prec=nlf.F32, batch=3, stream=s.cuda_stream)
+    _, st, status = p.ground_state(betas, gams, tau=0.25, eps0=1e-10, mixed=True)
+    assert status == nlf.OK
+    for k in range(3):
+        assert st[k]["iters"] > st[k]["iters_fp32"] + 1, st[k]
+        assert abs(st[k]["E"] - want[k]) <= 1e-9 * abs(want[k]), (k, st[k]["E"], want[k])
+    torch.cuda.synchronize()
+
+
 def test_gs_batched_workload_full():
     """Batched 2D ground-state workload at full size: 64 instances on [-16,16]^2 with grids drawn
     from {64^2, 128^2, 256^2}, beta ~ U[10,1000], gamma ~ U[0.5,2], Coulomb kernel, FP32 bulk and
