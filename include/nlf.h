@@ -89,7 +89,20 @@ typedef struct {
     int    split;    /* NLF_COULOMB3D only: nonzero evaluates the split form of Sec. 2.1,
                         Eq. '3.9', see below                                                    */
     double split_a;  /* width a of the partition p(k) = e^{-|k|^2/a}  (default (5.5/min L_i)^2) */
+    int    deterministic;   /* nonzero: bitwise-reproducible results, see below                  */
 } nlf_opts;
+
+/* Deterministic plans (opts.deterministic != 0; project addition, not in the paper).  By default
+ * the spreading adds a tile's sum with one floating-point atomic per cell and work item, so two
+ * calls agree only up to the order of those additions (and the 3D tile-gathered interpolation
+ * adds each tile's part of a node's sum atomically).  On a deterministic plan a tile's only work
+ * item stores its sums, the items of a tile of several store partial sums in slots of their own,
+ * and a second kernel adds those in a fixed order; the 3D interpolation is the plane-streamed
+ * kernel (one thread per node).  Every call, and every solver run on the plan, then gives the
+ * same bits, at some cost (512^2: 6% FP64, 14% FP32 per evaluation; 256^3 split: 3.5%).
+ * nlf_plan_set_spread returns NLF_EINVAL on such a plan and nlf_plan_autotune times its fixed
+ * decomposition without changing it.  Plans that have neither candidate lists nor neighbour bins
+ * (only the LDS-atomic scatter) return NLF_EUNSUPPORTED.                                       */
 
 /* Split evaluation (Sec. 2.1, Eq. '3.9', Fig. 'fig3.1'; opts.split != 0, 3D Coulomb only):
  *   u = I1 + I2,  I1 = (2 pi)^-3 int_D e^{ik.x} (1 - p(k)) / |k|^2 rhohat dk  over the cube
@@ -127,6 +140,7 @@ typedef struct {
     double eps;            /* confinement ratio (NLF_CONFINED2D), else 0                     */
     int split;             /* 1 for a split plan; then n_nodes/n_half/spread_* are the ball's */
     double split_a, split_P2;   /* partition width a and ball radius P2 (split plans)     */
+    int deterministic;     /* 1 for a deterministic plan                                     */
 } nlf_plan_info;
 
 /* Create a plan for the potential of `kernel` on `box` (Sec. 2.1 nodes and weights, Eq.

@@ -50,6 +50,13 @@ struct GItem {
     int count;         // candidates in this item
     long long start;   // first entry in the candidate list
     int only;          // 1: the tile's only item (the spreading stores its sums instead of adding)
+    int slot;          // deterministic plans, tiles of several items: the item's partial-sum slot
+};
+// Deterministic plans: a tile of several work items, whose items store their partial sums in the
+// slots [first, first + n) that k_tile_reduce then adds in slot order.
+struct TileRed {
+    int g0, g1, g2;
+    int first, n;
 };
 constexpr int kMChunk = 128;
 constexpr int kMItem = 1024;
@@ -85,6 +92,7 @@ struct nlf_plan {
     // split evaluation (3D Coulomb): I1 by this plan's FFTs, I2 by the ball plan `sub`
     int split = 0;
     double split_a = 0.0, split_P2 = 0.0;
+    int deterministic = 0;      // one work item per gather tile, plain stores; 3D plane-streamed interpolation
     nlf_plan* sub = nullptr;
     double pweight_a = 0.0;     // ball plan of a split: node weights times exp(-|k|^2 / a)
     int band = 0;               // ball plan of a split: spectrum cells |f_i| < band (3D) hold every
@@ -120,6 +128,13 @@ struct nlf_plan {
     nlf::GItem* gitems = nullptr;
     int ngitems = 0;
     nlf::XcdSplit item_split{};    // gather work items over the XCDs
+    // deterministic plans: per-item partial sums of the tiles of several items, and those tiles
+    double* pscratch = nullptr;    // [batch][nslots][256]
+    long long pscratch_slots = 0;  // slots allocated
+    long long nslots = 0;          // slots in use
+    nlf::TileRed* tred = nullptr;
+    long long tred_cap = 0;
+    int ntred = 0;
     double* iacc = nullptr;     // [batch][Mh] complex FP64: tile-gathered interpolation sums
     // spreading work decomposition (nlf_plan_set_spread / nlf_plan_autotune)
     int spread_mode = 0;        // NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER

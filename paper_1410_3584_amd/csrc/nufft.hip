@@ -474,7 +474,8 @@ template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS>
 __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
-                                                        const int* __restrict__ cand, double qq, BinArgs ba) {
+                                                        const int* __restrict__ cand, double qq, BinArgs ba,
+                                                        double* __restrict__ pscr, long long sstride) {
     constexpr int NW = 2 * KC / 64;   // waves; each multiplies KC / NW candidates of a block
     static_assert(KC % (4 * NW) == 0 && (KC / NW) % 8 == 0, "whole pairs of MFMA steps per wave");
     static_assert(2 * KC * 16 >= NW * 4 * 64, "wave partials fit S");
@@ -584,6 +585,10 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
 #pragma unroll
         for (int w = 0; w < NW; ++w) sum += S[(w * 4 + v) * 64 + l];
         const int i = 4 * v + (l >> 4), j = l & 15;
+        if (pscr && !it.only) {   // deterministic plan: the item's partial sum, every cell
+            pscr[(long long)b * sstride + (long long)it.slot * 256 + o] = sum;
+            continue;
+        }
         if (it.only || sum != 0.0) {
             const int x = o0 + (i & 7);
             long long cell;
@@ -597,6 +602,31 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
             else global_add<TG>(dst, (TG)sum);
         }
     }
+}
+
+// Deterministic plans: a tile of several work items adds its items' partial sums in slot order
+// and stores the result (cell o of the tile as in k_mspread's write-back), so no atomics decide the
+// order of the additions.
+template <typename TG, int DIM>
+__global__ void __launch_bounds__(256) k_tile_reduce(V2<TG>* __restrict__ grid, long long gstride,
+                                                     const double* __restrict__ pscr, long long sstride,
+                                                     const TileRed* __restrict__ tr, NodeArgs na) {
+    const TileRed r = tr[blockIdx.x];
+    const int b = blockIdx.y;
+    const int o = threadIdx.x;
+    const double* src = pscr + (long long)b * sstride + (long long)r.first * 256 + o;
+    double sum = 0.0;
+    for (int s = 0; s < r.n; ++s) sum += src[(long long)s * 256];
+    const int v = o >> 6, l = o & 63;
+    const int i = 4 * v + (l >> 4), j = l & 15;
+    const int x = r.g0 * 8 + (i & 7);
+    long long cell;
+    if (DIM == 2)
+        cell = (long long)x * na.Mr[1] + r.g1 * 16 + j;
+    else
+        cell = ((long long)x * na.Mr[1] + r.g1 * 4 + (j >> 2)) * na.Mr[2] + r.g2 * 4 + (j & 3);
+    TG* dst = reinterpret_cast<TG*>(grid + (long long)b * gstride + cell) + (i >> 3);
+    *dst = (TG)sum;
 }
 
 // ---- 2D interpolation on the FP64 matrix cores, one workgroup per bin of nodes -----------------
@@ -953,8 +983,9 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
         return NLF_OK;
     }
     // (the tile-gathered 3D interpolation reads the explicit candidate lists through the work
-    // items; with neighbour-bin items in use it takes the plane-streamed kernel)
-    if (p->use_gather && !p->items_bins) {
+    // items; with neighbour-bin items in use, or on a deterministic plan, whose sums must not go
+    // through atomics, it takes the plane-streamed kernel)
+    if (p->use_gather && !p->items_bins && !p->deterministic) {
         NLF_TRY(fill_zero(p, p->iacc, (size_t)p->batch * p->Mh * 2 * sizeof(double)));
         dim3 ggrid(8 * p->item_split.per, p->batch);
         const double qq = exp(-2.0 * p->gc.alpha);
@@ -993,22 +1024,42 @@ static int gather_spread_t(nlf_plan* p) {
         ba.n[i] = p->impl_n[i];
         ba.NB[i] = p->gng[i];
     }
+    // deterministic plans: the items of tiles of several store partial sums, added in order below
+    double* pscr = (p->deterministic && p->ntred > 0) ? p->pscratch : nullptr;
+    const long long sstride = p->nslots * 256;
     if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid
         double2* g64 = reinterpret_cast<double2*>(p->grid_b);
         if (p->dim == 2)
             hipLaunchKernelGGL((k_mspread<T, double, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
-                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba);
+                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
         else
             hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
-                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba);
+                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
     } else if (p->dim == 2) {
         hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
-                           na, p->gitems, p->ngitems, p->gcand, qq, ba);
+                           na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
     } else {
         hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
-                           na, p->gitems, p->ngitems, p->gcand, qq, ba);
+                           na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
     }
     NLF_HIP(hipGetLastError());
+    if (pscr) {
+        const dim3 rgrid(p->ntred, p->batch);
+        if (p->t1_prec != p->prec) {
+            double2* g64 = reinterpret_cast<double2*>(p->grid_b);
+            if (p->dim == 2)
+                hipLaunchKernelGGL((k_tile_reduce<double, 2>), rgrid, dim3(256), 0, p->stream, g64, p->G, pscr, sstride,
+                                   p->tred, na);
+            else
+                hipLaunchKernelGGL((k_tile_reduce<double, 3>), rgrid, dim3(256), 0, p->stream, g64, p->G, pscr, sstride,
+                                   p->tred, na);
+        } else if (p->dim == 2) {
+            hipLaunchKernelGGL((k_tile_reduce<T, 2>), rgrid, dim3(256), 0, p->stream, g, p->G, pscr, sstride, p->tred, na);
+        } else {
+            hipLaunchKernelGGL((k_tile_reduce<T, 3>), rgrid, dim3(256), 0, p->stream, g, p->G, pscr, sstride, p->tred, na);
+        }
+        NLF_HIP(hipGetLastError());
+    }
     return NLF_OK;
 }
 
@@ -1195,6 +1246,8 @@ int nlf_plan_set_spread(nlf_plan* p, int mode, int block, int item) {
     clear_error();
     if (!p) return set_error(NLF_EINVAL, "plan must not be NULL");
     if (p->sub) return nlf_plan_set_spread(p->sub, mode, block, item);   // the ball of a split
+    if (p->deterministic)
+        return set_error(NLF_EINVAL, "a deterministic plan keeps its one-item-per-tile spreading");
     if (mode != NLF_SPREAD_GATHER && mode != NLF_SPREAD_SCATTER && mode != NLF_SPREAD_BINS)
         return set_error(NLF_EINVAL, "spread mode must be NLF_SPREAD_GATHER, _SCATTER or _BINS");
     if (mode == NLF_SPREAD_SCATTER) {
@@ -1227,13 +1280,15 @@ int nlf_plan_autotune(nlf_plan* p, int reps, double* best_ms) {
     if (reps <= 0) reps = 5;
     struct Cfg { int mode, block, item; };
     std::vector<Cfg> cfgs;
-    if (p->use_gather)
+    if (p->deterministic)   // timed, not changed
+        cfgs.push_back({p->spread_mode, p->spread_kc, p->item_cap});
+    else if (p->use_gather)
         for (int block : {64, 128})
             for (int item : {256, 512, 1024, 2048}) cfgs.push_back({NLF_SPREAD_GATHER, block, item});
-    if (p->gather_impl_ok)
+    if (p->gather_impl_ok && !p->deterministic)
         for (int block : {64, 128})
             for (int item : {512, 1024, 2048}) cfgs.push_back({NLF_SPREAD_BINS, block, item});
-    if (p->t1_prec == p->prec) cfgs.push_back({NLF_SPREAD_SCATTER, p->spread_kc, p->item_cap});
+    if (p->t1_prec == p->prec && !p->deterministic) cfgs.push_back({NLF_SPREAD_SCATTER, p->spread_kc, p->item_cap});
     if (cfgs.empty()) return set_error(NLF_EINVAL, "no spreading decomposition to time");
     // node values 1: every tile the candidates reach receives a nonzero sum
     const long long nv = (long long)p->batch * p->Mh;
@@ -1254,7 +1309,7 @@ int nlf_plan_autotune(nlf_plan* p, int reps, double* best_ms) {
     Cfg bc = cfgs.front();
     int rc = NLF_OK;
     for (const Cfg& c : cfgs) {
-        if ((rc = nlf_plan_set_spread(p, c.mode, c.block, c.item)) != NLF_OK) break;
+        if (!p->deterministic && (rc = nlf_plan_set_spread(p, c.mode, c.block, c.item)) != NLF_OK) break;
         if ((rc = spread_only(p)) != NLF_OK) break;   // warm-up
         if (hipEventRecord(e0, p->stream) != hipSuccess) { rc = set_error(NLF_EHIP, "hipEventRecord failed"); break; }
         for (int r = 0; r < reps && rc == NLF_OK; ++r) rc = spread_only(p);
@@ -1273,7 +1328,7 @@ int nlf_plan_autotune(nlf_plan* p, int reps, double* best_ms) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != NLF_OK) return rc;
-    NLF_TRY(nlf_plan_set_spread(p, bc.mode, bc.block, bc.item));
+    if (!p->deterministic) NLF_TRY(nlf_plan_set_spread(p, bc.mode, bc.block, bc.item));
     if (best_ms) *best_ms = best;
     return NLF_OK;
 }

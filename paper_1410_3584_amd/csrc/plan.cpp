@@ -72,11 +72,29 @@ int set_items(nlf_plan* p, int cap, bool bins) {
             it.count = (int)std::min<long long>(cap, end - s0);
             it.start = bins ? s0 - beg : s0;   // bins: offset within the tile's candidate stream
             it.only = (end - beg <= cap) ? 1 : 0;
+            it.slot = -1;
             items.push_back(it);
         }
     }
     if ((long long)items.size() > p->gitems_cap)
         return set_error(NLF_EINVAL, "work-item size %d below the allocated minimum", cap);
+    // deterministic plans: the items of a tile of several store partial sums in consecutive
+    // slots (assigned in tile order, before the items are reordered for the launch)
+    std::vector<TileRed> tr;
+    long long nslots = 0;
+    if (p->deterministic) {
+        for (size_t i = 0; i < items.size();) {
+            size_t j = i;
+            while (j < items.size() && items[j].g0 == items[i].g0 && items[j].g1 == items[i].g1 &&
+                   items[j].g2 == items[i].g2)
+                ++j;
+            if (!items[i].only) {
+                tr.push_back({items[i].g0, items[i].g1, items[i].g2, (int)nslots, (int)(j - i)});
+                for (size_t k = i; k < j; ++k) items[k].slot = (int)nslots++;
+            }
+            i = j;
+        }
+    }
     XcdSplit xs;
     {
         std::vector<long long> cost(items.size());
@@ -89,6 +107,22 @@ int set_items(nlf_plan* p, int cap, bool bins) {
         NLF_HIP(hipMemcpyAsync(p->gitems, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice,
                                p->stream));
         NLF_HIP(hipStreamSynchronize(p->stream));   // `items` is released on return
+    }
+    if (p->deterministic) {
+        if (nslots > p->pscratch_slots) {
+            NLF_TRY(dev_alloc(p, (void**)&p->pscratch, (size_t)p->batch * nslots * 256 * sizeof(double)));
+            p->pscratch_slots = nslots;
+        }
+        if ((long long)tr.size() > p->tred_cap) {
+            NLF_TRY(dev_alloc(p, (void**)&p->tred, tr.size() * sizeof(TileRed)));
+            p->tred_cap = (long long)tr.size();
+        }
+        if (!tr.empty()) {
+            NLF_HIP(hipMemcpyAsync(p->tred, tr.data(), tr.size() * sizeof(TileRed), hipMemcpyHostToDevice, p->stream));
+            NLF_HIP(hipStreamSynchronize(p->stream));
+        }
+        p->nslots = nslots;
+        p->ntred = (int)tr.size();
     }
     p->ngitems = (int)items.size();
     p->item_split = xs;
@@ -317,6 +351,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     }
     p->prec = o ? o->prec : NLF_F64;
     if (p->prec != NLF_F64 && p->prec != NLF_F32) return set_error(NLF_EINVAL, "prec must be NLF_F64 or NLF_F32");
+    p->deterministic = (o && o->deterministic) ? 1 : 0;
     p->batch = (o && o->batch > 0) ? o->batch : 1;
     p->N = 1;
     p->G = 1;
@@ -615,6 +650,8 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
         // workloads measured: 1024 for FP64, msp 12, and 512 for FP32, msp 7; 256 on the small
         // solver grids; nlf_plan_autotune picks per plan); neighbour bins with 1024-candidate
         // items where the lists were not built
+        if (p->deterministic && !p->use_gather && !p->gather_impl_ok)
+            return set_error(NLF_EUNSUPPORTED, "a deterministic plan needs the gather spreading (lists or bins)");
         if (p->use_gather) {
             p->spread_mode = NLF_SPREAD_GATHER;
             int cap = 256;
@@ -875,6 +912,7 @@ int nlf_plan_get_info(const nlf_plan* p, nlf_plan_info* info) {
     info->spread_item = p->item_cap;
     info->gather_available = p->use_gather;
     info->bins_available = p->gather_impl_ok;
+    info->deterministic = p->deterministic;
     if (p->sub) {
         info->split = 1;
         info->split_a = p->split_a;

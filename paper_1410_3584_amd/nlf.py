@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("n_r", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_phi", ctypes.c_int), ("P", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("msp", ctypes.c_int), ("batch", ctypes.c_int), ("eps", ctypes.c_double),
-                ("split", ctypes.c_int), ("split_a", ctypes.c_double)]
+                ("split", ctypes.c_int), ("split_a", ctypes.c_double), ("deterministic", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -48,7 +48,7 @@ class PlanInfo(ctypes.Structure):
                 ("spread_block", ctypes.c_int), ("spread_item", ctypes.c_int),
                 ("gather_available", ctypes.c_int), ("bins_available", ctypes.c_int),
                 ("eps", ctypes.c_double), ("split", ctypes.c_int), ("split_a", ctypes.c_double),
-                ("split_P2", ctypes.c_double)]
+                ("split_P2", ctypes.c_double), ("deterministic", ctypes.c_int)]
 
 
 class Phys(ctypes.Structure):
@@ -148,10 +148,11 @@ def _ptr(t):
 class Plan:
     """A potential plan (nlf_plan_create).  kernel: COULOMB3D / COULOMB2D / LAPLACE2D /
     CONFINED2D (which needs eps > 0).  split=True (COULOMB3D): the split evaluation of Eq. '3.9'
-    with partition width split_a (0: default)."""
+    with partition width split_a (0: default).  deterministic=True: bitwise-reproducible results
+    (no floating-point atomics in the spreading or interpolation)."""
 
     def __init__(self, n, L, kernel, prec=F64, n_r=0, n_theta=0, n_phi=0, P=0.0, sigma=0.0,
-                 msp=0, batch=1, stream=None, eps=0.0, split=False, split_a=0.0):
+                 msp=0, batch=1, stream=None, eps=0.0, split=False, split_a=0.0, deterministic=False):
         import torch
         lib = load()
         self.torch = torch
@@ -160,7 +161,8 @@ class Plan:
         for i in range(len(n)):
             box.n[i] = int(n[i])
             box.L[i] = float(L[i])
-        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch, eps, 1 if split else 0, split_a)
+        opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch, eps, 1 if split else 0, split_a,
+                    1 if deterministic else 0)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream

@@ -170,6 +170,54 @@ def test_spread_decompositions_and_autotune(n, L, kernel, prec):
         assert rel_err(u, want_u) <= TOL[prec], mode
 
 
+@pytest.mark.parametrize("n,L,kernel,prec", [CASES[0], CASES[3], CASES[8], CASES[9], CASES[13]])
+def test_deterministic_plans_repeat_bitwise(n, L, kernel, prec):
+    """opts.deterministic: stored tile sums (partial sums of multi-item tiles added in a fixed
+    order by a second kernel) and, in 3D, the plane-streamed interpolation: no floating-point
+    atomics.  Two calls on one plan and calls
+    on two plans give the same bits; the result still meets the oracle's bar; the decomposition
+    cannot be changed and the autotuner only times it."""
+    print(f"[deterministic] n={n} kernel={kernel} prec={prec}", flush=True)
+    rho = _case_density(n, L, seed=13)
+    p1 = nlf.Plan(n, L, kernel, prec=prec, deterministic=True)
+    p2 = nlf.Plan(n, L, kernel, prec=prec, deterministic=True)
+    assert p1.info.deterministic == 1
+    r = to_dev(rho, prec)
+    a = p1.potential(r).cpu().numpy()
+    b = p1.potential(r).cpu().numpy()
+    c = p2.potential(r).cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+    want = op.potential(host_input(rho, prec), n, L, kernel)
+    assert rel_err(a.astype(np.float64), want) <= TOL[prec]
+    cfg = p1.spread_config()
+    with pytest.raises(nlf.NlfError):
+        p1.set_spread(nlf.SPREAD_GATHER, 64, 1024)
+    got_cfg, ms = p1.autotune(reps=2)
+    assert got_cfg == cfg and ms > 0.0
+    assert np.array_equal(p1.potential(r).cpu().numpy(), a)
+
+
+def test_deterministic_split_and_ground_state_repeat_bitwise():
+    """A deterministic split plan (its ball plan inherits the option) and ground states on a
+    deterministic plan (including the FP64 twin of the mixed schedule) repeat bit for bit."""
+    print("[deterministic split + ground state]", flush=True)
+    n, L = (64, 64, 64), (8.0, 8.0, 8.0)
+    X = inputs.mesh(n, L)
+    r = torch.tensor(np.exp(-(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)), dtype=torch.float64, device="cuda")
+    sp = nlf.Plan(n, L, nlf.COULOMB3D, split=True, deterministic=True)
+    a = sp.potential(r).cpu().numpy()
+    assert np.array_equal(a, sp.potential(r).cpu().numpy())
+    ref = nlf.Plan(n, L, nlf.COULOMB3D, split=True).potential(r).cpu().numpy()
+    assert rel_err(a, ref) <= 1e-12
+    g = nlf.Plan((64, 64), (16.0, 16.0), nlf.COULOMB2D, prec=nlf.F32, batch=2, deterministic=True)
+    runs = [g.ground_state([40.0, 300.0], [(1.0, 1.3), (1.0, 0.9)], tau=0.25, eps0=1e-10, mixed=True)
+            for _ in range(2)]
+    assert runs[0][2] == nlf.OK and runs[1][2] == nlf.OK
+    assert np.array_equal(runs[0][0].cpu().numpy(), runs[1][0].cpu().numpy())
+    assert [s["E"] for s in runs[0][1]] == [s["E"] for s in runs[1][1]]
+    assert [s["iters"] for s in runs[0][1]] == [s["iters"] for s in runs[1][1]]
+
+
 def test_neighbour_bins_match_explicit_lists_512():
     """At 512^2 (both decompositions available) the neighbour-bin gather and the explicit
     candidate lists give the same potential up to FP64 rounding (the extra candidates of the
