@@ -218,6 +218,23 @@ def test_deterministic_split_and_ground_state_repeat_bitwise():
     assert [s["iters"] for s in runs[0][1]] == [s["iters"] for s in runs[1][1]]
 
 
+def test_deterministic_neighbour_bins_256():
+    """A deterministic plain-ball plan at 256^3, where the spreading reads neighbour-bin streams:
+    two calls give the same bits, and the result equals the default plan's to rounding."""
+    print("[deterministic neighbour bins 256^3]", flush=True)
+    n, L = (256, 256, 256), (12.0, 12.0, 12.0)
+    rho = np.abs(inputs.psi0_phase_modulated(n, L, seed=0)) ** 2
+    rd = to_dev(rho, 0)
+    pd = nlf.Plan(n, L, nlf.COULOMB3D, deterministic=True)
+    assert pd.spread_config()[0] == nlf.SPREAD_BINS
+    a = pd.potential(rd)
+    b = pd.potential(rd)
+    assert torch.equal(a, b)
+    del pd
+    ref = nlf.Plan(n, L, nlf.COULOMB3D).potential(rd)
+    assert float((a - ref).abs().max() / ref.abs().max()) <= 1e-12
+
+
 def test_neighbour_bins_match_explicit_lists_512():
     """At 512^2 (both decompositions available) the neighbour-bin gather and the explicit
     candidate lists give the same potential up to FP64 rounding (the extra candidates of the
