@@ -257,7 +257,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", choices=["full", "prof", "prof3d"], default="full")
+    ap.add_argument("--mode", choices=["full", "prof", "prof3d", "profgs"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ground-states", action="store_true")
     ap.add_argument("--no-dynamics-3d", action="store_true")
@@ -286,6 +286,11 @@ def main():
         plan.evolve(psi, 50.0, (1.0, 1.0, 1.0), 1e-3, max(1, args.steps))
         torch.cuda.synchronize()
         print(json.dumps({"mode": "prof3d", "steps": args.steps}))
+        return
+    if args.mode == "profgs":
+        # the batched ground-state workload alone, for a kernel trace
+        gs = ground_states_per_s(torch, nlf, inputs)
+        print(json.dumps({"mode": "profgs", "ground_states_per_s": gs["value"]}))
         return
     n, L, rho, _ = inputs.potential_2d_512(seed=1)
     dev = "cuda"
