@@ -24,7 +24,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_ALU = 78.6e12      # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_FP64_ALU = 78.6e12      # FP64 vector and dense FP64 matrix peak: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 PEAK_FP32_ALU = 157.3e12     # published FP32 vector peak (packed); non-packed issue is half
 PEAK_HBM = 8.0e12
 
@@ -61,59 +61,66 @@ def blas_threads():
     return os.cpu_count()
 
 
-def cpu_baseline(n, L, rho, frac=2):
-    """Time the FP64 oracle (direct sums) on 1/frac of the node set of the K2 evaluation and
-    extrapolate linearly in the node count (both direct sums are linear in M)."""
+def oracle_reference(n, L, rho):
+    """The FP64 oracle on the bench's 2D workload: its type-2 direct sum at every node, the
+    Coulomb and Laplace node coefficients from it, and, timed as the CPU baseline, one
+    evaluation's two direct sums: the type-2 sum over all nodes and the type-1 sum over half of
+    them (the type-1 sum is linear in the node count, so its time is doubled)."""
     from oracle import potential as op
-    dp = op.DirectPotential(n, L, op.COULOMB2D)
-    M = dp.k.shape[0]
-    sel = slice(0, M // frac)
+    d2 = op.DirectPotential(n, L, op.COULOMB2D)
+    d3 = op.DirectPotential(n, L, op.LAPLACE2D)
+    k, M = d2.k, d2.k.shape[0]
     t0 = time.perf_counter()
-    rh = op.type2_direct(rho, n, L, dp.k[sel])
-    c = op.symbol_coeffs(op.COULOMB2D, dp.k[sel], dp.weight[sel], dp.kmag[sel], rh)
-    op.type1_direct(c, n, L, dp.k[sel])
-    dt = time.perf_counter() - t0
-    per_eval = dt * frac
-    return {"value": 1.0 / per_eval, "unit": "potential evals/s", "cores": blas_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 direct type-2 + symbol + type-1 sums over {M // frac} of {M} nodes "
-                      f"(1/{frac}) of one 512^2 Coulomb-2D evaluation, {dt:.1f} s, extrapolated x{frac}; "
-                      f"host: {cpu_model()}"}
+    rh = op.type2_direct(rho, n, L, k)
+    t_t2 = time.perf_counter() - t0
+    c2 = op.symbol_coeffs(op.COULOMB2D, k, d2.weight, d2.kmag, rh)
+    half = slice(0, M // 2)
+    t0 = time.perf_counter()
+    op.type1_direct(c2[half], n, L, k[half])
+    t_t1 = time.perf_counter() - t0
+    m0, m1 = op.moments(rho, n, L)
+    c3 = op.symbol_coeffs(op.LAPLACE2D, k, d3.weight, d3.kmag, rh, m0, m1, d3.sigma)
+    per_eval = t_t2 + 2.0 * t_t1
+    cpu = {"value": 1.0 / per_eval, "unit": "potential evals/s", "cores": blas_threads(), "kind": "oracle",
+           "sample": f"FP64 direct sums of one 512^2 Coulomb-2D evaluation: type-2 over all {M} nodes "
+                     f"({t_t2:.1f} s) and type-1 over {M // 2} of them ({t_t1:.1f} s, doubled); "
+                     f"host: {cpu_model()}"}
+    return {"k": k, "rhohat": rh, "c": {op.COULOMB2D: c2, op.LAPLACE2D: c3}, "m0": m0, "m1": m1,
+            "sigma": d3.sigma, "cpu": cpu}
 
 
-def sampled_parity(plan, rho_dev, rho_host, kernel, prec, rng):
-    """Relative error of the GPU potential vs the oracle at sampled grid points, using the GPU's
-    node values checked themselves at sampled nodes (same scheme as the parity tests)."""
+def parity_vs_oracle(plan, rho_dev, kernel, ref, pts):
+    """Relative errors of what was timed against the oracle's own sums (no GPU value enters the
+    oracle's side): the type-2 stage at every node, and the potential at the sampled grid points
+    `pts`, where the oracle sums its node coefficients over the whole node set."""
     from oracle import potential as op
     n, L = plan.n, plan.L
-    k, w = plan.nodes()
     rh = plan.type2(rho_dev).cpu().numpy().astype(np.complex128)
-    sel = rng.choice(len(k), 64, replace=False)
-    e2 = np.max(np.abs(rh[sel] - op.type2_direct(rho_host, n, L, k[sel]))) / np.max(np.abs(rh))
-    kmag = np.linalg.norm(k, axis=1)
-    m0 = m1 = None
-    if kernel == op.LAPLACE2D:
-        m0, m1 = op.moments(rho_host, n, L)
-    c = op.symbol_coeffs(kernel, k, w, kmag, rh, m0, m1, plan.info.sigma)
+    e2 = float(np.max(np.abs(rh - ref["rhohat"])) / np.max(np.abs(ref["rhohat"])))
     u = plan.potential(rho_dev).cpu().numpy().astype(np.float64)
     xs, _ = op.grid_axes(n, L)
-    pts = [tuple(rng.integers(0, n[i]) for i in range(2)) for _ in range(24)]
-    err = 0.0
+    k, c = ref["k"], ref["c"][kernel]
+    want = []
     for p in pts:
         x = np.array([xs[0][p[0]], xs[1][p[1]]])
         v = float(np.real(np.sum(c * np.exp(1j * (k @ x)))))
         if kernel == op.LAPLACE2D:
             X, Y = np.array([[x[0]]]), np.array([[x[1]]])
-            ax, ay = op.u12(X, Y, plan.info.sigma)
-            v += m0 * op.u11(X, Y, plan.info.sigma)[0, 0] - (m1[0] * ax[0, 0] + m1[1] * ay[0, 0])
-        err = max(err, abs(u[p] - v))
-    return float(max(e2, err / np.max(np.abs(u))))
+            ax, ay = op.u12(X, Y, ref["sigma"])
+            m1 = ref["m1"]
+            v += ref["m0"] * op.u11(X, Y, ref["sigma"])[0, 0] - (m1[0] * ax[0, 0] + m1[1] * ay[0, 0])
+        want.append(v)
+    want = np.array(want)
+    got = np.array([u[p] for p in pts])
+    eu = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+    return {"type2_all_nodes": e2, "potential_sampled": eu}
 
 
 def stage_algorithmic(plan, stage):
     """Algorithmic work of one launch of a stage: (amount, unit, bound).
-    interp / spread: 4 flops per stencil touch (two real FMAs on a complex value), w^d touches
-    per node, M/2 nodes; FFT stages: bytes that must cross HBM once per pass."""
+    interp / spread: 5 flops per stencil touch (one weight product and two real FMAs on the
+    complex value), w^d touches per node, M/2 nodes; FFT stages: bytes that must cross HBM once
+    per pass."""
     info = plan.info
     d = info.dim
     w = 2 * info.msp
@@ -123,7 +130,7 @@ def stage_algorithmic(plan, stage):
     N = int(np.prod(n))
     G = int(np.prod([2 * v for v in n]))
     if stage in ("interp", "spread"):
-        return 4.0 * (w ** d) * info.n_half * info.batch, "flop", "alu"
+        return 5.0 * (w ** d) * info.n_half * info.batch, "flop", "alu"
     if stage == "fft_fwd":   # rows: read rho, write n0 oversampled rows; cols: read them, write grid
         rows = n[0] * 2 * n[1] * es_c
         return float(N * es_r + rows + rows + G * es_c) * info.batch, "byte", "hbm"
@@ -212,17 +219,18 @@ def ground_states_per_s(torch, nlf, inputs):
                                  for k, v in tuned.items()}}
 
 
-def dynamics_3d(torch, nlf, inputs, steps=20):
-    """Third workload: 3D Coulomb-cubic time splitting on 256^3 of [-12,12]^3, harmonic trap,
-    normalised Gaussian with seeded phase modulation, beta = 50, dt = 1e-3, Strang steps, FP64,
-    with the split evaluation of the potential (Eq. '3.9'); one potential of the plain ball
-    evaluation is timed beside it.  Reports steps/s over `steps` timed steps after 2 untimed
-    ones, and the mass/energy drift over them."""
+def dynamics_3d(torch, nlf, inputs, steps=1000, diag_every=100):
+    """Third workload: 3D Coulomb-cubic time splitting on 256^3 of [-12,12]^3, harmonic trap
+    V = |x|^2/2, normalised Gaussian with seeded phase modulation, dt = 1e-3, Strang steps, FP64,
+    the potential by the split evaluation (Eq. '3.9'); one potential of the plain ball evaluation
+    is timed beside it.  For beta = +50 and beta = -10: `steps` timed steps from psi0 (after 2
+    untimed steps on a copy), with mass and energy every `diag_every` steps (their evaluations
+    are inside the timed region)."""
     n, L = (256,) * 3, (12.0,) * 3
-    psi0 = inputs.psi0_phase_modulated(n, L, seed=0)
-    psi = torch.tensor(psi0, dtype=torch.complex128, device="cuda")
-    rho = (psi.abs() ** 2).contiguous()
-    out = {"workload": "3D dynamics, 256^3 on [-12,12]^3, Coulomb, beta 50, dt 1e-3, Strang, FP64"}
+    psi0 = torch.tensor(inputs.psi0_phase_modulated(n, L, seed=0), dtype=torch.complex128, device="cuda")
+    rho = (psi0.abs() ** 2).contiguous()
+    out = {"workload": f"3D dynamics, 256^3 on [-12,12]^3, Coulomb, dt 1e-3, {steps} Strang steps, FP64, "
+                       "split evaluation"}
     ball = nlf.Plan(n, L, nlf.COULOMB3D)
     ball.potential(rho)
     torch.cuda.synchronize()
@@ -240,15 +248,23 @@ def dynamics_3d(torch, nlf, inputs, steps=20):
         plan.potential(rho, u)
     torch.cuda.synchronize()
     out["split_potential_ms"] = 1e3 * (time.perf_counter() - t0) / 5
-    plan.evolve(psi, 50.0, (1.0, 1.0, 1.0), 1e-3, 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    diag = plan.evolve(psi, 50.0, (1.0, 1.0, 1.0), 1e-3, steps, diag_every=steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out.update({"steps": steps, "steps_per_s": steps / dt,
-                "mass_drift": float(abs(diag[-1, 0, 0] - diag[0, 0, 0])),
-                "energy_rel_drift": float(abs(diag[-1, 0, 1] - diag[0, 0, 1]) / abs(diag[0, 0, 1]))})
+    for beta in (50.0, -10.0):
+        warm = psi0.clone()
+        plan.evolve(warm, beta, (1.0, 1.0, 1.0), 1e-3, 2)
+        del warm
+        psi = psi0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        diag = plan.evolve(psi, beta, (1.0, 1.0, 1.0), 1e-3, steps, diag_every=diag_every)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mass, en = diag[:, 0, 0], diag[:, 0, 1]
+        out[f"beta_{beta:+g}"] = {
+            "steps": steps, "steps_per_s": steps / dt, "seconds": dt,
+            "t_final": steps * 1e-3,
+            "mass_drift_max": float(np.max(np.abs(mass - mass[0]))),
+            "energy_rel_drift_max": float(np.max(np.abs(en - en[0])) / abs(en[0])),
+            "energy_every_100": [float(v) for v in en]}
     return out
 
 
@@ -262,6 +278,7 @@ def main():
     ap.add_argument("--no-ground-states", action="store_true")
     ap.add_argument("--no-dynamics-3d", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--dyn-steps", type=int, default=1000, help="Strang steps per beta of the 3D dynamics leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
@@ -293,6 +310,9 @@ def main():
         print(json.dumps({"mode": "profgs", "ground_states_per_s": gs["value"]}))
         return
     n, L, rho, _ = inputs.potential_2d_512(seed=1)
+    # rounded to FP32 values once: the FP64 and FP32 legs then evaluate the same density, and one
+    # oracle result checks both
+    rho = np.asarray(rho, dtype=np.float32).astype(np.float64)
     dev = "cuda"
     r64 = torch.tensor(rho, dtype=torch.float64, device=dev)
     r32 = torch.tensor(rho, dtype=torch.float32, device=dev)
@@ -345,22 +365,24 @@ def main():
 
     # ---- live per-stage timing (HIP events on the plan's stream) for the roofline ----
     stage_avg = {}
-    for key in (("K2", 0), ("K3", 0)):
+    for key in (("K2", 0), ("K3", 0), ("K2", 1), ("K3", 1)):
         p = plans[key]
         p.set_profiling(True)
         p.stage_times(reset=True)
         for _ in range(args.steps):
-            p.potential(rin[0], outs[0])
+            p.potential(rin[key[1]], outs[key[1]])
         st = p.stage_times(reset=True)
         p.set_profiling(False)
-        stage_avg[key[0]] = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st.items()}
+        stage_avg[key[0] + ("_f32" if key[1] else "")] = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st.items()}
     # dominant kernel: largest average launch time in the FP64 Laplace evaluation
     dom_stage = max(("interp", "spread", "fft_fwd", "fft_inv"), key=lambda s: stage_avg["K3"][s])
     amount, unit, bound = stage_algorithmic(plans[("K3", 0)], dom_stage)
     avg_s = stage_avg["K3"][dom_stage] * 1e-3
     if bound == "alu":
+        # the FP64 stencil kernels are dense contractions on the FP64 matrix cores (whose dense peak,
+        # 78.6 TFLOP/s, equals the FP64 vector peak)
         achieved = amount / avg_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_ALU / 1e12, "unit": "TFLOP/s",
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_ALU / 1e12, "unit": "TFLOP/s",
                 "frac": achieved * 1e12 / PEAK_FP64_ALU}
     else:
         achieved = amount / avg_s / 1e9
@@ -370,21 +392,23 @@ def main():
     roof["kernel"] = dom_stage
     roof["avg_launch_ms"] = stage_avg["K3"][dom_stage]
 
-    # ---- parity of what was timed (sampled, vs the FP64 oracle) ----
+    # ---- parity of what was timed, against the oracle's own full sums ----
+    ref = oracle_reference(n, L, rho)
     rng = np.random.default_rng(0)
-    rho32_host = np.asarray(rho, dtype=np.float32).astype(np.float64)
+    pts = [tuple(int(v) for v in rng.integers(0, n[0], size=2)) for _ in range(48)] + [(256, 256), (0, 0)]
     parity = {
-        "K2_f64": sampled_parity(plans[("K2", 0)], r64, rho, 2, 0, rng),
-        "K3_f64": sampled_parity(plans[("K3", 0)], r64, rho, 3, 0, rng),
-        "K2_f32": sampled_parity(plans[("K2", 1)], r32, rho32_host, 2, 1, rng),
-        "K3_f32": sampled_parity(plans[("K3", 1)], r32, rho32_host, 3, 1, rng),
+        "K2_f64": parity_vs_oracle(plans[("K2", 0)], r64, nlf.COULOMB2D, ref, pts),
+        "K3_f64": parity_vs_oracle(plans[("K3", 0)], r64, nlf.LAPLACE2D, ref, pts),
+        "K2_f32": parity_vs_oracle(plans[("K2", 1)], r32, nlf.COULOMB2D, ref, pts),
+        "K3_f32": parity_vs_oracle(plans[("K3", 1)], r32, nlf.LAPLACE2D, ref, pts),
     }
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(n, L, rho)
+    cpu = None if args.no_cpu_baseline else ref["cpu"]
     gs = None if args.no_ground_states else ground_states_per_s(torch, nlf, inputs)
-    dyn = None if args.no_dynamics_3d else dynamics_3d(torch, nlf, inputs)
+    dyn = None if args.no_dynamics_3d else dynamics_3d(torch, nlf, inputs, steps=args.dyn_steps)
 
     value = 2 * args.steps / t64
+    msp64, msp32 = plans[("K2", 0)].info.msp, plans[("K2", 1)].info.msp
     out = {
         "metric": "potential evals/sec at rel err 1e-10 (FP64) / 1e-6 (FP32); ground states/sec",
         "value": value,
@@ -398,10 +422,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "2D potential, 512^2 grid on [-16,16]^2, exp(-(x^2+4y^2)) + 8 seeded bumps, "
-                               "kernels 1/(2 pi|x|) and -ln|x|/(2 pi) alternating, 512x1024 polar nodes, w=24",
-                   "grid": [512, 512], "nodes": 524288, "msp_f64": 12, "msp_f32": 7},
-        "fp32": {"value": 2 * args.steps / t32, "unit": "potential evals/s", "msp": 7},
+        "config": {"workload": "2D potential, 512^2 grid on [-16,16]^2, exp(-(x^2+4y^2)) + 8 seeded bumps "
+                               "(values rounded to FP32), kernels 1/(2 pi|x|) and -ln|x|/(2 pi) alternating, "
+                               f"512x1024 polar nodes, w={2 * msp64} (FP64) / {2 * msp32} (FP32)",
+                   "grid": [512, 512], "nodes": 524288, "msp_f64": msp64, "msp_f32": msp32},
+        "fp32": {"value": 2 * args.steps / t32, "unit": "potential evals/s", "msp": msp32,
+                 "ratio_to_f64": t64 / t32},
         "batched": batched,
         "parity_rel_err": parity,
         "stage_ms": {k: {s: round(v, 5) for s, v in d.items()} for k, d in stage_avg.items()},

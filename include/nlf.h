@@ -90,7 +90,23 @@ typedef struct {
                         Eq. '3.9', see below                                                    */
     double split_a;  /* width a of the partition p(k) = e^{-|k|^2/a}  (default (5.5/min L_i)^2) */
     int    deterministic;   /* nonzero: bitwise-reproducible results, see below                  */
+    int    check_finite;    /* nonzero: nlf_potential and nlf_type2 wait for their work and return
+                               NLF_ENONFINITE if the density held a NaN or Inf, see below         */
 } nlf_opts;
+
+/* Non-finite densities.  The pass that loads the density into the oversampled grid (the first
+ * step of nlf_potential and nlf_type2, and of the potentials inside the solvers) sets a device flag
+ * of the plan when a value is NaN or +-Inf; the potential of such a density is not defined and the
+ * outputs then hold NaN.  On a plan created with opts.check_finite != 0, nlf_potential and
+ * nlf_type2 synchronise the plan's stream at their end, return NLF_ENONFINITE if the flag was set
+ * by this call, and clear it.  With the default 0 they return as soon as their work is enqueued
+ * and do not look at the flag.  The gradient-flow solver reports NLF_ENONFINITE from its own
+ * FP64 reductions whatever the option.
+ *
+ * Workspace cap.  If the environment variable NLF_MAX_WORKSPACE_BYTES holds a positive integer,
+ * every device allocation a plan makes for itself (at nlf_plan_create, and the solver workspace
+ * at the first solver call) fails with NLF_ENOMEM once the plan's total would exceed it; it is
+ * read at each allocation.                                                                      */
 
 /* Deterministic plans (opts.deterministic != 0; project addition, not in the paper).  By default
  * the spreading adds a tile's sum with one floating-point atomic per cell and work item, so two

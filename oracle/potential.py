@@ -213,9 +213,12 @@ class DirectPotential:
             self._u11 = u11(X, Y, self.sigma)
             self._u12 = u12(X, Y, self.sigma)
 
-    def __call__(self, rho, return_parts=False):
+    def __call__(self, rho, return_parts=False, rhohat=None):
+        """u for the density rho.  rhohat: the type-2 sum of this same rho on this node set
+        (`type2_direct`), when a caller already has it (two kernels of one density share it)."""
         rho = np.asarray(rho, dtype=np.float64).reshape(self.n)
-        rhohat = type2_direct(rho, self.n, self.L, self.k)
+        if rhohat is None:
+            rhohat = type2_direct(rho, self.n, self.L, self.k)
         m0 = m1 = None
         if self.kernel == LAPLACE2D:
             m0, m1 = moments(rho, self.n, self.L)

@@ -219,6 +219,7 @@ struct RowsArgs {
     double sigma, L0, L1, h0, h1;
     // LOAD_RHO, 2D Laplace: per-workgroup partial sums of rho, x rho, y rho ([batch][grid.x][3])
     double* mom_part;
+    int* nonfinite;        // LOAD_RHO: set to 1 when a density value is NaN or +-Inf (may be NULL)
 };
 
 // sum of v over the workgroup (blockDim.x a multiple of 64, <= 1024); every thread gets it
@@ -296,6 +297,12 @@ __global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
                     dv[u] = decl[j];
                 }
             }
+        }
+        if (a.nonfinite) {   // a NaN or Inf anywhere in the density: flag the plan (rare path)
+            bool bad = false;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) bad = bad || !isfinite(rv[u]);
+            if (bad) atomicOr(a.nonfinite, 1);
         }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
@@ -729,6 +736,7 @@ static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
     r.tw = p->tw_big[2];
     r.nlines = p->n[0] * p->n[1];
     r.half = H;
+    r.nonfinite = p->nf_flag;
     NLF_TRY((launch_rows<T, -1, LOAD_RHO, STORE_GRID>(p, r, p->batch)));
     ColsArgs c{};
     c.grid = p->grid_a; c.gstride = p->G; c.n = p->Mr[1]; c.inner = H;
@@ -775,6 +783,7 @@ static int type2_forward_t(nlf_plan* p, const void* rho) {
     r.tw = p->tw_big[d - 1];
     r.nlines = (d == 2) ? p->n[0] : p->n[0] * p->n[1];
     r.band = p->band;
+    r.nonfinite = p->nf_flag;
     // 2D Laplace: the moments m0, m1 of rho (Alg. 1) ride along the row pass
     const bool mom = (p->kernel == NLF_LAPLACE2D);
     if (mom) {
@@ -918,6 +927,21 @@ static int full_t(nlf_plan* p, void* data, int batch) {
 int fft_full(nlf_plan* p, void* data, int dir, int batch) {
     if (p->prec == NLF_F64) return dir < 0 ? full_t<double, -1>(p, data, batch) : full_t<double, 1>(p, data, batch);
     return dir < 0 ? full_t<float, -1>(p, data, batch) : full_t<float, 1>(p, data, batch);
+}
+
+__global__ void k_clear_flag(int* f) { *f = 0; }
+
+// Wait for the plan's work, read the density load pass's non-finite flag into *seen and clear it.
+int read_nonfinite(nlf_plan* p, int* seen) {
+    int v = 0;
+    NLF_HIP(hipMemcpyAsync(&v, p->nf_flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+    NLF_HIP(hipStreamSynchronize(p->stream));
+    *seen = v;
+    if (v) {
+        hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, p->stream, p->nf_flag);
+        NLF_HIP(hipGetLastError());
+    }
+    return NLF_OK;
 }
 
 int fill_zero(nlf_plan* p, void* ptr, size_t bytes) {

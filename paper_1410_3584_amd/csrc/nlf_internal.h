@@ -93,6 +93,8 @@ struct nlf_plan {
     int split = 0;
     double split_a = 0.0, split_P2 = 0.0;
     int deterministic = 0;      // one work item per gather tile, plain stores; 3D plane-streamed interpolation
+    int check_finite = 0;       // nlf_potential / nlf_type2 read the non-finite flag before returning
+    int* nf_flag = nullptr;     // device: set to 1 by the density load pass on a NaN / Inf value
     nlf_plan* sub = nullptr;
     double pweight_a = 0.0;     // ball plan of a split: node weights times exp(-|k|^2 / a)
     int band = 0;               // ball plan of a split: spectrum cells |f_i| < band (3D) hold every
@@ -191,6 +193,7 @@ int fft_type1_inverse(nlf_plan* p, void* u, bool add_u1);     // grid_b -> u (pr
 int fft_split_i1(nlf_plan* p, const void* rho, void* u);      // u += I1 of a split (Eq. '3.9')
 int fft_full(nlf_plan* p, void* data, int dir, int batch);    // n-grid complex FFT in place, all axes
 int fill_zero(nlf_plan* p, void* ptr, size_t bytes);
+int read_nonfinite(nlf_plan* p, int* seen);                   // sync the stream, read and clear nf_flag
 int set_items(nlf_plan* p, int cap, bool bins);               // rebuild the gather work items
 
 // NUFFT stages (nufft.hip)

@@ -20,6 +20,7 @@
 // node set is symmetric under k -> -k (even n_phi, symmetric Gauss-Legendre in cos theta).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "nlf_internal.h"
 
@@ -604,6 +605,144 @@ __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid
     }
 }
 
+// The same gather on the FP32 matrix cores, for FP32 plans (v_mfma_f32_16x16x4f32, twice the FP64
+// matrix rate).  The rows of A and B are built as in k_mspread (weights in FP64, rounded to FP32)
+// and kept transposed in LDS, SA[j][k] / SB[j][k] with a pitch of KC + 4 floats: the per-thread
+// stores of one row hit consecutive banks, and the MFMA operand reads (16 rows j, 4 candidates k)
+// are conflict-free within each half-wave.  Each block of KC candidates is summed in FP32 (the
+// wave's K/NW candidates over four product chains); the blocks are added in FP64, and the item's
+// sum goes to the FP64 spreading grid of the FP32 plan.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// row of the 16 x 16 result held by accumulator register v of lane l (column l mod 16) of
+// v_mfma_f32_16x16x4f32
+__device__ __forceinline__ int mfma32_row(int v, int l) { return 4 * (l >> 4) + v; }
+
+template <int MSP, int DIM, int KC, bool BINS>
+__global__ void __launch_bounds__(2 * KC, 4) k_mspread32(double2* __restrict__ grid, long long gstride,
+                                                          const float2* __restrict__ cbuf, long long cstride,
+                                                          NodeArgs na, const GItem* __restrict__ items, int nitems,
+                                                          const int* __restrict__ cand, double qq, BinArgs ba,
+                                                          double* __restrict__ pscr, long long sstride) {
+    constexpr int NW = 2 * KC / 64;
+    constexpr int KP = KC + 4;
+    static_assert((KC / NW) % 16 == 0, "whole groups of four MFMA steps per wave");
+    __shared__ float SA[16 * KP], SB[16 * KP];
+    __shared__ double R[NW * 4 * 64];
+    const int iid = split_id(na.isplit);
+    if (iid < 0) return;
+    const GItem it = items[iid];
+    const int b = blockIdx.y;
+    const int t = threadIdx.x;
+    const int o0 = it.g0 * 8;
+    const int o1 = it.g1 * (DIM == 2 ? 16 : 4);
+    const int o2 = it.g2 * 4;
+    const int k = t & (KC - 1);
+    const bool is_a = t < KC;
+    const int wv = t >> 6, lane = t & 63;
+    const int r = lane & 15, kq = lane >> 4;
+    const int kb = wv * (KC / NW);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ int nb_pref[BINS ? kMaxNbrBins + 1 : 1], nb_tmp[BINS ? kMaxNbrBins + 1 : 1];
+    __shared__ int nb_start[BINS ? kMaxNbrBins : 1];
+    int nbn = 0;
+    if (BINS) nbn = bin_table<2 * KC>(ba, it.g0, it.g1, it.g2, nb_pref, nb_tmp, nb_start);
+    double sa = 0.0, sb = 0.0;
+    float2 cv = make_float2(0.0f, 0.0f);
+    auto fetch = [&](int base) {
+        if (base + k < it.count) {
+            const int node = BINS ? bin_node(nb_pref, nb_start, nbn, (int)it.start + base + k)
+                                  : cand[it.start + base + k];
+            if (is_a) {
+                sa = na.s[0][node];
+                cv = cbuf[(long long)b * cstride + node];
+            } else {
+                sa = na.s[1][node];
+                if (DIM == 3) sb = na.s[2][node];
+            }
+        }
+    };
+    fetch(0);
+    for (int base = 0; base < it.count; base += KC) {
+        const int cnt = min(KC, it.count - base);
+        if (base > 0) __syncthreads();   // the previous block's products have read SA, SB
+        float row[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) row[j] = 0.0f;
+        if (k < cnt) {
+            if (is_a) {
+                double w0[8];
+                tile_weights<MSP, 8>(sa, o0, na.Mr[0], na.gc.alpha, qq, w0);
+                const double cx = (double)cv.x, cy = (double)cv.y;
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    row[x] = (float)(cx * w0[x]);
+                    row[8 + x] = (float)(cy * w0[x]);
+                }
+            } else if (DIM == 2) {
+                double w1[16];
+                tile_weights<MSP, 16>(sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
+#pragma unroll
+                for (int j = 0; j < 16; ++j) row[j] = (float)w1[j];
+            } else {
+                double w1[4], w2[4];
+                tile_weights<MSP, 4>(sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
+                tile_weights<MSP, 4>(sb, o2, na.Mr[2], na.gc.alpha, qq, w2);
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+#pragma unroll
+                    for (int z = 0; z < 4; ++z) row[4 * y + z] = (float)(w1[y] * w2[z]);
+            }
+        }
+        float* dst = is_a ? SA : SB;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[j * KP + k] = row[j];
+        __syncthreads();
+        fetch(base + KC);
+        if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
+            constexpr int kSteps = KC / NW / 4;
+            f4_t c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0, c2 = c0, c3 = c0;
+#pragma unroll
+            for (int q = 0; q < kSteps; q += 4) {
+                const int off = r * KP + kb + 4 * q + kq;
+                c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(SA[off], SB[off], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(SA[off + 4], SB[off + 4], c1, 0, 0, 0);
+                c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(SA[off + 8], SB[off + 8], c2, 0, 0, 0);
+                c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(SA[off + 12], SB[off + 12], c3, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += (double)((c0[v] + c1[v]) + (c2[v] + c3[v]));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) R[(wv * 4 + v) * 64 + lane] = acc[v];
+    __syncthreads();
+    for (int o = t; o < 256; o += 2 * KC) {
+        const int v = o >> 6, l = o & 63;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += R[(w * 4 + v) * 64 + l];
+        const int i = mfma32_row(v, l), j = l & 15;
+        if (pscr && !it.only) {   // deterministic plan: the item's partial sum, every cell, in the
+                                  // slot order k_tile_reduce reads (the FP64 product's layout)
+            pscr[(long long)b * sstride + (long long)it.slot * 256 + 64 * (i >> 2) + 16 * (i & 3) + j] = sum;
+            continue;
+        }
+        if (it.only || sum != 0.0) {
+            const int x = o0 + (i & 7);
+            long long cell;
+            if (DIM == 2)
+                cell = (long long)x * na.Mr[1] + o1 + j;
+            else
+                cell = ((long long)x * na.Mr[1] + o1 + (j >> 2)) * na.Mr[2] + o2 + (j & 3);
+            double* d = reinterpret_cast<double*>(grid + (long long)b * gstride + cell) + (i >> 3);
+            if (it.only) *d = sum;
+            else global_add<double>(d, sum);
+        }
+    }
+}
+
 // Deterministic plans: a tile of several work items adds its items' partial sums in slot order
 // and stores the result (cell o of the tile as in k_mspread's write-back), so no atomics decide the
 // order of the additions.
@@ -778,6 +917,145 @@ __global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ g
         if (ka == 0 && jn < ch.count) {
             const int node = ch.start + jn;
             epilogue<T>(ea, b, node, pre, pim, na.s[0][node], na.s[1][node]);
+        }
+    }
+}
+
+// The same per-bin interpolation on the FP32 matrix cores for FP32 plans: the window planes in LDS
+// as FP32 (PX = 8 mod 32 floats, plane pitch PL = 32 mod 64 floats: the A-operand reads of a wave,
+// 8 rows x 4 columns x 2 planes, then fall on distinct banks per half-wave), the nodes' y-weights
+// from the same FP64 recurrence rounded to FP32, H = G B by v_mfma_f32_16x16x4f32 with FP32 sums
+// over the <= KS column steps, and the contraction with the x-weights, the lane exchanges and the
+// symbol epilogue in FP64.  Lane (ia, ka) holds H[4 ka + v][ia] in register v (rows (comp, x) =
+// (ka / 2, 4 (ka mod 2) + v) of each 8-row block), so it needs the node's x-weights of rows
+// 8 rb + 4 (ka mod 2) + v, taken from a unit-step Gaussian recurrence.
+template <int MSP>
+__global__ void __launch_bounds__(256, 3) k_binterp2_32(const float2* __restrict__ grid, long long gstride,
+                                                        NodeArgs na, EpiArgs ea, double qq4, double qq1,
+                                                        double2* __restrict__ zero, long long zero16) {
+    constexpr int WX = 8 + 2 * MSP - 1, RBX = (WX + 7) / 8;
+    constexpr int WY = 16 + 2 * MSP - 1, KS = (WY + 3) / 4;
+    constexpr int NRW = 8 * RBX, NCW = 4 * KS + 4;
+    constexpr int PX = NRW + ((8 - NRW % 32) + 32) % 32;
+    constexpr int PL0 = NCW * PX;
+    constexpr int PL = PL0 + ((32 - PL0 % 64) + 64) % 64;
+    __shared__ float Gp[2 * PL];
+    __shared__ double nd[kChunk][2];
+    __shared__ int noff[kChunk][2];
+    if (zero) {
+        const long long nwg = (long long)gridDim.x * gridDim.y;
+        const long long wg = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const long long per = (zero16 + nwg - 1) / nwg;
+        const long long e = min(zero16, (wg + 1) * per);
+        for (long long i = wg * per + threadIdx.x; i < e; i += 256) zero[i] = make_double2(0.0, 0.0);
+    }
+    const int cid = split_id(na.csplit);
+    if (cid < 0) return;
+    const Chunk ch = na.chunks[cid];
+    const int b = blockIdx.y;
+    const int t = threadIdx.x;
+    const float2* g = grid + (long long)b * gstride;
+    const int o0 = ch.t0 * 8 - (MSP - 1), o1 = ch.t1 * 16 - (MSP - 1);
+    constexpr int PER = (NRW * NCW + 255) / 256;
+    float2 gv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        if (idx < NRW * NCW) {
+            const int c = 4 * (idx / (4 * NRW)) + (idx & 3), r = (idx >> 2) % NRW;
+            gv[u] = g[(long long)wrap(o0 + r, na.Mr[0]) * na.Mr[1] + wrap(o1 + c, na.Mr[1])];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = t + 256 * u;
+        if (idx < NRW * NCW) {
+            const int c = 4 * (idx / (4 * NRW)) + (idx & 3), r = (idx >> 2) % NRW;
+            Gp[c * PX + r] = gv[u].x;
+            Gp[PL + c * PX + r] = gv[u].y;
+        }
+    }
+    if (t < ch.count) {
+        const int node = ch.start + t;
+        const double s0 = na.s[0][node], s1 = na.s[1][node];
+        const double f0 = floor(s0), f1 = floor(s1);
+        nd[t][0] = s0 - f0;
+        nd[t][1] = s1 - f1;
+        noff[t][0] = wrap((int)f0, na.Mr[0]) - ch.t0 * 8;
+        noff[t][1] = wrap((int)f1, na.Mr[1]) - ch.t1 * 16;
+    }
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63;
+    const int ia = lane & 15, ka = lane >> 4;
+    const double alpha = na.gc.alpha;
+    const float* arow = &Gp[(ia >> 3) * PL + ka * PX + (ia & 7)];
+    const int xb = 4 * (ka & 1);   // first x row of this lane within each 8-row block
+    for (int k0 = 16 * wv; k0 < ch.count; k0 += 64) {
+        const int jn = k0 + ia;
+        const int c0 = noff[k0][1], c1 = noff[min(k0 + 15, ch.count - 1)][1];
+        const int ksg = (c1 - c0 + 2 * MSP + 3) >> 2;
+        float bv[KS];
+        double wx[RBX][4];
+        if (jn < ch.count) {
+            const double d0 = nd[jn][0], d1 = nd[jn][1];
+            const int rx0 = noff[jn][0], ry0 = noff[jn][1];
+            {   // y-weights of columns c0 + 4 st + ka
+                const int q0 = c0 + ka - ry0;
+                const double x0 = (double)(q0 - (MSP - 1)) - d1;
+                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
+#pragma unroll
+                for (int st = 0; st < KS; ++st) {
+                    const int q = q0 + 4 * st;
+                    bv[st] = (q >= 0 && q < 2 * MSP) ? (float)gg : 0.0f;
+                    gg *= rr;
+                    rr *= qq4;
+                }
+            }
+            {   // x-weights of rows X = xb + 8 rb + v by the unit-step recurrence over X = xb .. 8 RBX - 1
+                const int q0 = xb - rx0;
+                const double x0 = (double)(q0 - (MSP - 1)) - d0;
+                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (2.0 * x0 + 1.0));
+#pragma unroll
+                for (int rb = 0; rb < RBX; ++rb) {
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int q = q0 + 8 * rb + v;
+                        if (v < 4) wx[rb][v] = (q >= 0 && q < 2 * MSP) ? gg : 0.0;
+                        gg *= rr;
+                        rr *= qq1;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int st = 0; st < KS; ++st) bv[st] = 0.0f;
+#pragma unroll
+            for (int rb = 0; rb < RBX; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) wx[rb][v] = 0.0;
+        }
+        f4_t h[RBX];
+#pragma unroll
+        for (int rb = 0; rb < RBX; ++rb) h[rb] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        const float* acol = arow + c0 * PX;
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            if (st < ksg) {   // uniform over the wave
+#pragma unroll
+                for (int rb = 0; rb < RBX; ++rb)
+                    h[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(acol[8 * rb + 4 * st * PX], bv[st], h[rb], 0, 0, 0);
+            }
+        }
+        double part = 0.0;   // real part (ka < 2) or imaginary part (ka >= 2) of the node's sum
+#pragma unroll
+        for (int rb = 0; rb < RBX; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part += wx[rb][v] * (double)h[rb][v];
+        part += __shfl_xor(part, 16);
+        const double pim = __shfl_down(part, 32);
+        if (ka == 0 && jn < ch.count) {
+            const int node = ch.start + jn;
+            epilogue<float>(ea, b, node, part, pim, na.s[0][node], na.s[1][node]);
         }
     }
 }
@@ -976,9 +1254,16 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
         dim3 grid(8 * p->chunk_split.per, p->batch);
         const double qq4 = exp(-32.0 * p->gc.alpha);
         const size_t bbytes = (size_t)p->batch * p->G * elem_size(p->t1_prec);   // a multiple of 16
-        hipLaunchKernelGGL((k_binterp2<T, MSP>), grid, dim3(256), 0, p->stream,
-                           reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4,
-                           zero_b ? (double2*)p->grid_b : nullptr, (long long)(bbytes / 16));
+        double2* zb = zero_b ? (double2*)p->grid_b : nullptr;
+        if constexpr (std::is_same<T, float>::value) {   // FP32 plans: the FP32 matrix cores
+            hipLaunchKernelGGL((k_binterp2_32<MSP>), grid, dim3(256), 0, p->stream,
+                               reinterpret_cast<const float2*>(p->grid_a), p->G, na, ea, qq4, exp(-2.0 * p->gc.alpha),
+                               zb, (long long)(bbytes / 16));
+        } else {
+            hipLaunchKernelGGL((k_binterp2<T, MSP>), grid, dim3(256), 0, p->stream,
+                               reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4, zb,
+                               (long long)(bbytes / 16));
+        }
         NLF_HIP(hipGetLastError());
         return NLF_OK;
     }
@@ -1027,14 +1312,20 @@ static int gather_spread_t(nlf_plan* p) {
     // deterministic plans: the items of tiles of several store partial sums, added in order below
     double* pscr = (p->deterministic && p->ntred > 0) ? p->pscratch : nullptr;
     const long long sstride = p->nslots * 256;
-    if (p->t1_prec != p->prec) {   // FP32 node values, FP64 spreading grid
-        double2* g64 = reinterpret_cast<double2*>(p->grid_b);
-        if (p->dim == 2)
-            hipLaunchKernelGGL((k_mspread<T, double, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
-                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
-        else
-            hipLaunchKernelGGL((k_mspread<T, double, MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
-                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value) {
+        if (p->t1_prec != p->prec) {   // FP32 node values: FP32 matrix cores, FP64 spreading grid
+            double2* g64 = reinterpret_cast<double2*>(p->grid_b);
+            if (p->dim == 2)
+                hipLaunchKernelGGL((k_mspread32<MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
+                                   c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+            else
+                hipLaunchKernelGGL((k_mspread32<MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
+                                   c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+            done = true;
+        }
+    }
+    if (done) {
     } else if (p->dim == 2) {
         hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
                            na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
@@ -1212,22 +1503,43 @@ using namespace nlf;
 
 extern "C" {
 
+// check_finite plans: the flag is cleared before the call's work (a solver may have left it set)
+// and read, with a stream synchronisation, after it
+static int finite_begin(nlf_plan* p) {
+    if (!p->check_finite) return NLF_OK;
+    int seen = 0;
+    return read_nonfinite(p, &seen);
+}
+static int finite_end(nlf_plan* p) {
+    if (!p->check_finite) return NLF_OK;
+    int seen = 0;
+    NLF_TRY(read_nonfinite(p, &seen));
+    if (seen) return set_error(NLF_ENONFINITE, "the density holds a NaN or Inf value");
+    return NLF_OK;
+}
+
 int nlf_potential(nlf_plan* p, const void* rho, void* u) {
     clear_error();
     if (!p || !rho || !u) return set_error(NLF_EINVAL, "plan, rho and u must not be NULL");
     if (rho == u) return set_error(NLF_EINVAL, "rho and u may not alias");
-    return potential(p, rho, u);
+    NLF_TRY(finite_begin(p));
+    NLF_TRY(potential(p, rho, u));
+    return finite_end(p);
 }
 
 int nlf_type2(nlf_plan* p, const void* rho, void* rhohat) {
     clear_error();
     if (!p || !rho || !rhohat) return set_error(NLF_EINVAL, "plan, rho and rhohat must not be NULL");
+    NLF_TRY(finite_begin(p));
     if (p->sub) {   // the ball of a split
         p->sub->stream = p->stream;
-        return nlf_type2(p->sub, rho, rhohat);
+        NLF_TRY(fft_type2_forward(p->sub, rho));
+        NLF_TRY(interp(p->sub, MODE_TYPE2, rhohat, false));
+    } else {
+        NLF_TRY(fft_type2_forward(p, rho));
+        NLF_TRY(interp(p, MODE_TYPE2, rhohat, false));
     }
-    NLF_TRY(fft_type2_forward(p, rho));
-    return interp(p, MODE_TYPE2, rhohat, false);
+    return finite_end(p);
 }
 
 int nlf_type1(nlf_plan* p, const void* c, void* u) {

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -131,9 +132,22 @@ int set_items(nlf_plan* p, int cap, bool bins) {
     return NLF_OK;
 }
 
+// NLF_MAX_WORKSPACE_BYTES: an optional cap on a plan's own device memory (0 or unset: none)
+static long long workspace_cap() {
+    const char* v = std::getenv("NLF_MAX_WORKSPACE_BYTES");
+    if (!v || !*v) return 0;
+    char* end = nullptr;
+    const long long c = std::strtoll(v, &end, 10);
+    return (end && *end == '\0' && c > 0) ? c : 0;
+}
+
 int dev_alloc(nlf_plan* p, void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) bytes = 256;
+    const long long cap = workspace_cap();
+    if (cap > 0 && p->workspace_bytes + (long long)bytes > cap)
+        return set_error(NLF_ENOMEM, "allocating %zu bytes would take the plan's workspace to %lld bytes, above "
+                         "NLF_MAX_WORKSPACE_BYTES = %lld", bytes, p->workspace_bytes + (long long)bytes, cap);
     hipError_t e = hipMalloc(ptr, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -330,6 +344,9 @@ static int build_split(nlf_plan* p, const nlf_box* box, int kernel, const nlf_op
     NLF_TRY(dev_alloc(p, (void**)&p->mom, (size_t)p->batch * 4 * sizeof(double)));
     p->red_bytes = (size_t)p->batch * 1024 * 8 * sizeof(double);
     NLF_TRY(dev_alloc(p, (void**)&p->red, p->red_bytes));
+    NLF_TRY(dev_alloc(p, (void**)&p->nf_flag, sizeof(int)));
+    NLF_HIP(hipMemsetAsync(p->nf_flag, 0, sizeof(int), p->stream));
+    p->sub->nf_flag = p->nf_flag;   // both density loads of a split (I1's and the ball's) report here
     p->spread_mode = p->sub->spread_mode;
     return NLF_OK;
 }
@@ -352,6 +369,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     p->prec = o ? o->prec : NLF_F64;
     if (p->prec != NLF_F64 && p->prec != NLF_F32) return set_error(NLF_EINVAL, "prec must be NLF_F64 or NLF_F32");
     p->deterministic = (o && o->deterministic) ? 1 : 0;
+    p->check_finite = (o && o->check_finite) ? 1 : 0;
     p->batch = (o && o->batch > 0) ? o->batch : 1;
     p->N = 1;
     p->G = 1;
@@ -762,6 +780,8 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     }
     p->red_bytes = (size_t)p->batch * 1024 * 8 * sizeof(double);
     NLF_TRY(dev_alloc(p, (void**)&p->red, p->red_bytes));
+    NLF_TRY(dev_alloc(p, (void**)&p->nf_flag, sizeof(int)));
+    NLF_HIP(hipMemsetAsync(p->nf_flag, 0, sizeof(int), p->stream));
     return NLF_OK;
 }
 

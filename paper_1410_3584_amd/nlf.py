@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("n_r", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_phi", ctypes.c_int), ("P", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("msp", ctypes.c_int), ("batch", ctypes.c_int), ("eps", ctypes.c_double),
-                ("split", ctypes.c_int), ("split_a", ctypes.c_double), ("deterministic", ctypes.c_int)]
+                ("split", ctypes.c_int), ("split_a", ctypes.c_double), ("deterministic", ctypes.c_int),
+                ("check_finite", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -149,10 +150,12 @@ class Plan:
     """A potential plan (nlf_plan_create).  kernel: COULOMB3D / COULOMB2D / LAPLACE2D /
     CONFINED2D (which needs eps > 0).  split=True (COULOMB3D): the split evaluation of Eq. '3.9'
     with partition width split_a (0: default).  deterministic=True: bitwise-reproducible results
-    (no floating-point atomics in the spreading or interpolation)."""
+    (no floating-point atomics in the spreading or interpolation).  check_finite=True: potential()
+    and type2() wait for their work and raise NlfError(ENONFINITE) on a NaN/Inf density."""
 
     def __init__(self, n, L, kernel, prec=F64, n_r=0, n_theta=0, n_phi=0, P=0.0, sigma=0.0,
-                 msp=0, batch=1, stream=None, eps=0.0, split=False, split_a=0.0, deterministic=False):
+                 msp=0, batch=1, stream=None, eps=0.0, split=False, split_a=0.0, deterministic=False,
+                 check_finite=False):
         import torch
         lib = load()
         self.torch = torch
@@ -162,7 +165,7 @@ class Plan:
             box.n[i] = int(n[i])
             box.L[i] = float(L[i])
         opts = Opts(prec, n_r, n_theta, n_phi, P, sigma, msp, batch, eps, 1 if split else 0, split_a,
-                    1 if deterministic else 0)
+                    1 if deterministic else 0, 1 if check_finite else 0)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
@@ -269,6 +272,7 @@ class Plan:
         self._check_in(c, self.cdtype, self.M * self.batch)
         if out is None:
             out = self.torch.empty(self._shape(), dtype=self.rdtype, device=c.device)
+        self._check_in(out, self.rdtype, int(np.prod(self.n)) * self.batch)
         _check(load().nlf_type1(self._h, _ptr(c), _ptr(out)))
         return out
 
@@ -300,6 +304,7 @@ class Plan:
             self._check_in(psi0, self.rdtype, N)
         if out is None:
             out = self.torch.empty(self._shape(), dtype=self.rdtype, device="cuda")
+        self._check_in(out, self.rdtype, N)
         stats = (GsStats * self.batch)()
         st = load().nlf_ground_state(self._h, phys, ctypes.byref(gf), _ptr(psi0), _ptr(out), stats)
         if st not in (OK, ENOCONV):
@@ -324,18 +329,25 @@ class Plan:
 
 
 def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
-                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=False):
+                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=False, psi0=None):
     """nlf_ground_state_batch over several plans (one per grid size); betas[i] / gammas[i] give
-    the per-field parameters of plan i.  Returns ([psi_i], [[stats]], status)."""
+    the per-field parameters of plan i; psi0[i] (or None, or psi0=None for all) its initial
+    guesses.  Returns ([psi_i], [[stats]], status)."""
     import torch
     lib = load()
     k = len(plans)
+    if len(betas) != k or len(gammas) != k or (psi0 is not None and len(psi0) != k):
+        raise ValueError("betas, gammas (and psi0) must give one entry per plan")
     hs = (ctypes.c_void_p * k)(*[p._h.value for p in plans])
     phys_keep = [p._phys(b, g, None) for p, b, g in zip(plans, betas, gammas)]
     phys = (ctypes.POINTER(Phys) * k)(*[ctypes.cast(a, ctypes.POINTER(Phys)) for a in phys_keep])
     outs = [torch.empty(p._shape(), dtype=p.rdtype, device="cuda") for p in plans]
     psi = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
-    psi0 = (ctypes.c_void_p * k)(*([None] * k))
+    starts = [None] * k if psi0 is None else list(psi0)
+    for p, s0 in zip(plans, starts):
+        if s0 is not None:
+            p._check_in(s0, p.rdtype, int(np.prod(p.n)) * p.batch)
+    psi0 = (ctypes.c_void_p * k)(*[None if s0 is None else s0.data_ptr() for s0 in starts])
     st_keep = [(GsStats * p.batch)() for p in plans]
     stats = (ctypes.POINTER(GsStats) * k)(*[ctypes.cast(a, ctypes.POINTER(GsStats)) for a in st_keep])
     gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch,
@@ -392,19 +404,34 @@ class Model:
         _check(load().nlf_ws_set_standardisation(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                                  sd.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
+    def _check_xt(self, x, t=None):
+        """x: (B, n_in) and t: (B, n_out), contiguous FP32 CUDA tensors; returns B."""
+        def ok(a, cols):
+            return (a.is_cuda and a.dtype == self.torch.float32 and a.is_contiguous() and a.dim() == 2
+                    and a.shape[1] == cols and a.shape[0] >= 1)
+        if not ok(x, self.n_in):
+            raise ValueError(f"x must be a contiguous CUDA float32 tensor of shape (B, {self.n_in}), "
+                             f"got {x.dtype} {tuple(x.shape)} on {x.device}")
+        if t is not None and not (ok(t, self.n_out) and t.shape[0] == x.shape[0]):
+            raise ValueError(f"t must be a contiguous CUDA float32 tensor of shape ({x.shape[0]}, {self.n_out}), "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+        return int(x.shape[0])
+
     def forward(self, x):
-        B = x.shape[0]
+        B = self._check_xt(x)
         y = self.torch.empty((B, self.n_out), dtype=self.torch.float32, device=x.device)
         _check(load().nlf_ws_forward(self._h, B, _ptr(x), _ptr(y)))
         return y
 
     def loss_grad(self, x, t):
+        B = self._check_xt(x, t)
         g = self.torch.empty(self.n_params, dtype=self.torch.float32, device=x.device)
         loss = ctypes.c_double()
-        _check(load().nlf_ws_loss_grad(self._h, x.shape[0], _ptr(x), _ptr(t), _ptr(g), ctypes.byref(loss)))
+        _check(load().nlf_ws_loss_grad(self._h, B, _ptr(x), _ptr(t), _ptr(g), ctypes.byref(loss)))
         return loss.value, g
 
     def train(self, x, t, epochs, minibatch=0, lr=1e-3):
+        self._check_xt(x, t)
         hist = np.zeros(max(epochs, 1))
         _check(load().nlf_ws_train(self._h, x.shape[0], _ptr(x), _ptr(t), int(epochs), int(minibatch),
                                    float(lr), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
