@@ -346,6 +346,21 @@ int nlf_ws_predict(nlf_model* model, nlf_plan* plan, const nlf_phys* phys, int c
 int nlf_ws_ground_state(nlf_model* model, int coarse_n, nlf_plan* plan, const nlf_phys* phys,
                         const nlf_gf_opts* gf, void* psi_dev, nlf_gs_stats* stats, int* used_host);
 
+/* ---- no-allocation entry point (project addition, not in the paper) -------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, serving loops that
+ * forbid allocation.  Computes exactly what nlf_potential computes, with the same kernels, but the
+ * call's scratch (the two oversampled grids, the node values, the 3D node accumulators, the moments
+ * and their partial sums) lives in a fixed device array of the library of NLF_NOALLOC_MAX_BYTES
+ * bytes, of which every GPU the library runs on holds its own copy until the process ends.  The
+ * call allocates nothing (no hipMalloc, no hipFree, no allocating library routine).
+ * A plan whose scratch would exceed the array returns NLF_EINVAL; split and deterministic plans
+ * return NLF_EUNSUPPORTED.  All calls on one GPU share that GPU's array and it keeps the last
+ * call's contents (each call writes every scratch value before reading it): calls that overlap in
+ * time on one GPU, from other streams or threads, race, and the caller must serialise them.
+ * Arguments, stream and errors as nlf_potential.                                                 */
+#define NLF_NOALLOC_MAX_BYTES (64ull << 20)
+int nlf_potential_noalloc(nlf_plan* plan, const void* rho_dev, void* u_dev);
+
 /* Message for the calling thread's last error ("" if none).                                 */
 const char* nlf_last_error(void);
 /* Static description of a status code.                                                      */

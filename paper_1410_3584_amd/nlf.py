@@ -22,7 +22,8 @@ EXPORTS = ["nlf_plan_create", "nlf_plan_destroy", "nlf_plan_get_info", "nlf_plan
            "nlf_last_error", "nlf_strerror", "nlf_version", "nlf_plan_set_profiling",
            "nlf_plan_stage_times", "nlf_ws_create", "nlf_ws_destroy", "nlf_ws_num_params", "nlf_ws_params",
            "nlf_ws_set_standardisation", "nlf_ws_forward", "nlf_ws_loss_grad", "nlf_ws_train",
-           "nlf_ws_predict", "nlf_ws_ground_state", "nlf_plan_set_spread", "nlf_plan_autotune"]
+           "nlf_ws_predict", "nlf_ws_ground_state", "nlf_plan_set_spread", "nlf_plan_autotune",
+           "nlf_potential_noalloc"]
 STAGES = ["moments", "fft_fwd", "interp", "zero", "spread", "fft_inv"]
 SPREAD_GATHER, SPREAD_SCATTER, SPREAD_BINS = 0, 1, 2
 
@@ -99,6 +100,7 @@ def load(path=LIB_PATH):
     lib.nlf_potential.argtypes = [vp, vp, vp]
     lib.nlf_type2.argtypes = [vp, vp, vp]
     lib.nlf_type1.argtypes = [vp, vp, vp]
+    lib.nlf_potential_noalloc.argtypes = [vp, vp, vp]
     lib.nlf_ground_state.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(GfOpts), vp, vp,
                                      ctypes.POINTER(GsStats)]
     lib.nlf_evolve.argtypes = [vp, ctypes.POINTER(Phys), ctypes.POINTER(TsOpts), vp, dp]
