@@ -260,6 +260,8 @@ typedef struct {
     int    mixed;
     double eps_switch;
     int    graph;
+    int    persistent;   /* nlf_ground_state_batch: nonzero runs an eligible batch in one persistent
+                            launch (see there); 0 (default): one host thread per plan              */
 } nlf_gf_opts;
 
 typedef struct {
@@ -270,6 +272,8 @@ typedef struct {
     double residual;        /* last max|phi^{n+1}-phi^n|/tau                                 */
     double virial;          /* 2E_kin - 2E_pot + (E_int | beta/(4 pi)), Sec. 3.2             */
     double mass;            /* h^d sum |phi|^2                                               */
+    int    persistent;      /* 1 if the field was solved inside the single persistent launch of
+                               nlf_ground_state_batch (see there), 0 otherwise                  */
 } nlf_gs_stats;
 
 /* Ground state by the backward-Euler normalized gradient flow, Fourier pseudospectral in
@@ -286,10 +290,20 @@ int nlf_ground_state(nlf_plan* plan, const nlf_phys* phys, const nlf_gf_opts* gf
 
 /* Several ground-state solves at once, e.g. one plan per grid size of a batch of instances of
  * uneven size: plan i (with its own batch B_i) takes phys[i] (B_i entries), psi0_dev[i] (or NULL),
- * psi_dev[i] and stats[i] (B_i entries), exactly as nlf_ground_state.  The solves run
- * concurrently, one host thread per plan; give the plans distinct streams so that their kernels
- * overlap on the device.  Returns the first error, else NLF_ENOCONV if any field did not reach
- * eps0, else NLF_OK.                                                                         */
+ * psi_dev[i] and stats[i] (B_i entries), exactly as nlf_ground_state.
+ * One persistent launch (project addition): with gf->persistent set, when every plan is 2D with at
+ * most 256 points per axis, all plans share one precision and the default stencil widths, spread by
+ * gather lists and are neither deterministic nor profiled, and gf->graph is 0 (at most 16 plans),
+ * the whole batch runs in ONE cooperative kernel launch on the first plan's stream.  The kernels of one outer step
+ * of each plan are recorded once and replayed on the device for every plan together, with grid
+ * barriers between them; the inner and outer loops, the retirement of each field at eps0 and,
+ * with gf->mixed, the switch of every plan from its FP32 stage to its FP64 twin run on the device.
+ * The launch is ordered after the earlier work of every plan's stream and before its later work.
+ * stats[].persistent is 1 for fields solved this way.  The launch's grid barriers (about a hundred
+ * per outer step) each cost a write-back of every XCD's L2, so on the batches measured this path is
+ * slower than the default.  Otherwise the solves run concurrently, one host thread per plan (give
+ * the plans distinct streams so that their kernels overlap).  Returns the
+ * first error, else NLF_ENOCONV if any field did not reach eps0, else NLF_OK.                  */
 int nlf_ground_state_batch(int count, nlf_plan* const plans[], const nlf_phys* const phys[],
                            const nlf_gf_opts* gf, const void* const psi0_dev[], void* const psi_dev[],
                            nlf_gs_stats* const stats[]);

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 
+#include "exec.h"
 #include "nlf_internal.h"
 
 namespace nlf {
@@ -130,6 +131,11 @@ int set_items(nlf_plan* p, int cap, bool bins) {
     p->item_cap = cap;
     p->items_bins = bins ? 1 : 0;
     return NLF_OK;
+}
+
+Recorder*& recorder() {
+    thread_local Recorder* r = nullptr;
+    return r;
 }
 
 // NLF_MAX_WORKSPACE_BYTES: an optional cap on a plan's own device memory (0 or unset: none)

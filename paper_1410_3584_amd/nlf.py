@@ -60,7 +60,8 @@ class Phys(ctypes.Structure):
 class GfOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("eps0", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("check_every", ctypes.c_int), ("cg_tol", ctypes.c_double), ("cg_max_iter", ctypes.c_int),
-                ("mixed", ctypes.c_int), ("eps_switch", ctypes.c_double), ("graph", ctypes.c_int)]
+                ("mixed", ctypes.c_int), ("eps_switch", ctypes.c_double), ("graph", ctypes.c_int),
+                ("persistent", ctypes.c_int)]
 
 
 class GsStats(ctypes.Structure):
@@ -68,7 +69,7 @@ class GsStats(ctypes.Structure):
                 ("E", ctypes.c_double),
                 ("mu", ctypes.c_double), ("Ekin", ctypes.c_double), ("Epot", ctypes.c_double),
                 ("Eint", ctypes.c_double), ("residual", ctypes.c_double), ("virial", ctypes.c_double),
-                ("mass", ctypes.c_double)]
+                ("mass", ctypes.c_double), ("persistent", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -331,10 +332,12 @@ class Plan:
 
 
 def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=100000, check_every=10,
-                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=False, psi0=None):
+                       cg_tol=0.0, cg_max_iter=0, mixed=False, eps_switch=0.0, graph=False, psi0=None,
+                       persistent=False):
     """nlf_ground_state_batch over several plans (one per grid size); betas[i] / gammas[i] give
     the per-field parameters of plan i; psi0[i] (or None, or psi0=None for all) its initial
-    guesses.  Returns ([psi_i], [[stats]], status)."""
+    guesses; persistent=True: one persistent launch for an eligible batch.  Returns ([psi_i],
+    [[stats]], status)."""
     import torch
     lib = load()
     k = len(plans)
@@ -353,7 +356,7 @@ def ground_state_batch(plans, betas, gammas, tau=1e-2, eps0=1e-10, max_iter=1000
     st_keep = [(GsStats * p.batch)() for p in plans]
     stats = (ctypes.POINTER(GsStats) * k)(*[ctypes.cast(a, ctypes.POINTER(GsStats)) for a in st_keep])
     gf = GfOpts(tau, eps0, max_iter, check_every, cg_tol, cg_max_iter, 1 if mixed else 0, eps_switch,
-                    1 if graph else 0)
+                1 if graph else 0, 1 if persistent else 0)
     status = lib.nlf_ground_state_batch(k, hs, phys, ctypes.byref(gf), psi0, psi, stats)
     if status not in (OK, ENOCONV):
         _check(status)

@@ -197,19 +197,21 @@ def test_gs_graph_replay_matches_direct_launches(prec, mixed):
     assert rel_err(plan.potential(rho).cpu().numpy(), u_between.cpu().numpy()) < tol_u
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_gs_batch_over_plans_of_uneven_size(graph):
+@pytest.mark.parametrize("graph,persistent", [(False, False), (True, False), (False, True)])
+def test_gs_batch_over_plans_of_uneven_size(graph, persistent):
     """nlf_ground_state_batch: two grid sizes, two fields each, solved concurrently on separate
-    streams (each thread capturing its own step graphs when graph=True); every field equals its
-    individual solve."""
-    print(f"[gs batch over plans] graph={graph}", flush=True)
+    streams (each thread capturing its own step graphs when graph=True) or in one persistent
+    launch; every field equals its individual solve."""
+    print(f"[gs batch over plans] graph={graph} persistent={persistent}", flush=True)
     sizes = [(64, 64), (128, 128)]
     betas = [[3.0, 30.0], [10.0, 1.0]]
     gams = [[(1.0, 1.0), (1.0, 1.5)], [(1.0, 0.7), (1.0, 1.2)]]
     streams = [torch.cuda.Stream() for _ in sizes]
     plans = [nlf.Plan(n, (16.0, 16.0), nlf.COULOMB2D, batch=2, stream=s.cuda_stream) for n, s in zip(sizes, streams)]
-    outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.5, eps0=1e-10, graph=graph)
+    outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.5, eps0=1e-10, graph=graph,
+                                                 persistent=persistent)
     assert status == nlf.OK
+    assert all(s["persistent"] == (1 if persistent else 0) for a in stats for s in a)
     for i, n in enumerate(sizes):
         for j in range(2):
             single = nlf.Plan(n, (16.0, 16.0), nlf.COULOMB2D)
@@ -251,8 +253,9 @@ def test_gs_batch_uneven_plans_vs_oracle(oracle_uneven, prec, mixed):
     plans = [nlf.Plan(n, UNEVEN_L, kernel, prec=prec, batch=2, stream=s.cuda_stream)
              for (n, kernel, _, _), s in zip(UNEVEN, streams)]
     outs, stats, status = nlf.ground_state_batch(plans, [u[2] for u in UNEVEN], [u[3] for u in UNEVEN],
-                                                 tau=UNEVEN_TAU, eps0=UNEVEN_EPS0, mixed=mixed)
+                                                 tau=UNEVEN_TAU, eps0=UNEVEN_EPS0, mixed=mixed, persistent=True)
     assert status == nlf.OK
+    assert all(s["persistent"] == 1 for a in stats for s in a)   # one persistent launch for the batch
     state_tol = 1e-9 if prec == nlf.F64 else 2.0 ** -22
     for i, (n, kernel, betas, gams) in enumerate(UNEVEN):
         for j, beta in enumerate(betas):
@@ -304,14 +307,16 @@ def test_plans_on_nonblocking_streams_while_the_device_is_busy():
     torch.cuda.synchronize()
 
 
-def test_gs_batched_workload_full():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_gs_batched_workload_full(persistent):
     """Batched 2D ground-state workload at full size: 64 instances on [-16,16]^2 with grids drawn
     from {64^2, 128^2, 256^2}, beta ~ U[10,1000], gamma ~ U[0.5,2], Coulomb kernel, FP32 bulk and
     FP64 polish, autotuned spreading, solved concurrently (one plan and stream per size).  Every
     field reaches the 1e-10 residual; every field of the 64^2 and 128^2 groups and a sampled one
     of the 256^2 group equal their own FP64 solve (a field whose FP64 stage stopped early keeps
-    an FP32-quality energy, off by 1e-8 to 1e-6)."""
-    print("[gs batched workload]", flush=True)
+    an FP32-quality energy, off by 1e-8 to 1e-6).  Both the threaded batch and the one persistent
+    launch."""
+    print(f"[gs batched workload] persistent={persistent}", flush=True)
     inst = inputs.ground_state_batch_2d(seed=3, count=64)
     groups = {}
     for d in inst:
@@ -325,9 +330,10 @@ def test_gs_batched_workload_full():
     betas = [[d["beta"] for d in groups[k]] for k in keys]
     gams = [[d["gamma"] for d in groups[k]] for k in keys]
     outs, stats, status = nlf.ground_state_batch(plans, betas, gams, tau=0.25, eps0=1e-10, max_iter=5000,
-                                                 mixed=True)
+                                                 mixed=True, persistent=persistent)
     assert status == nlf.OK
     assert sum(len(a) for a in stats) == 64
+    assert all(s["persistent"] == (1 if persistent else 0) for a in stats for s in a)
     assert max(s["residual"] for a in stats for s in a) <= 1e-10
     rng = np.random.default_rng(0)
     for i, k in enumerate(keys):
