@@ -138,6 +138,7 @@ struct nlf_plan {
     long long tred_cap = 0;
     int ntred = 0;
     double* iacc = nullptr;     // [batch][Mh] complex FP64: tile-gathered interpolation sums
+    void* wtab = nullptr;       // 2D gather plans: [Mh][8] (g, r) tile start weights (nufft.hip)
     // spreading work decomposition (nlf_plan_set_spread / nlf_plan_autotune)
     int spread_mode = 0;        // NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER
     int spread_kc = 64;         // candidates per block of the gather kernel
@@ -202,6 +203,8 @@ int interp(nlf_plan* p, int mode, void* out, bool zero_b);
 int spread(nlf_plan* p);                                      // cbuf -> grid_b
 int fold_c(nlf_plan* p, const void* c);                       // canonical full c -> cbuf (sorted, folded)
 int potential(nlf_plan* p, const void* rho, void* u);
+bool weight_table_fits(const nlf_plan* p);                    // 2D plans whose spreading can use a weight table
+int build_weight_table(nlf_plan* p);                          // allocate and fill p->wtab (needs p->s)
 
 // harmonic-oscillator Gaussian initial guesses of the plan's fields (unnormalised), solvers.hip
 int ho_guess(nlf_plan* p, const nlf_phys* phys, void* out);

@@ -41,7 +41,44 @@ static NodeArgs node_args(const nlf_plan* p) {
     na.gc = p->gc;
     na.csplit = p->chunk_split;
     na.isplit = p->item_split;
+    na.wtab = reinterpret_cast<const double2*>(p->wtab);
     return na;
+}
+
+// The weight table of a 2D plan (see NodeArgs::wtab): for sorted node m and axis i, the gather
+// tiles (GT_0 = 8, GT_1 = 16 cells) from the one holding the stencil's first cell l0 - msp + 1 on,
+// four of them, each stored at slot (tile index mod 4).  A stencil overlaps at most four
+// consecutive tiles, so every tile whose candidate list holds the node finds its own values.
+__global__ void k_weight_table(const double* __restrict__ s0, const double* __restrict__ s1, long long Mh, int Mr0,
+                               int Mr1, int msp, double alpha, double2* __restrict__ wt) {
+    for (long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x; m < Mh; m += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            const double s = ax == 0 ? s0[m] : s1[m];
+            const int Mr = ax == 0 ? Mr0 : Mr1, gt = ax == 0 ? 8 : 16, ng = Mr / gt;
+            const int first = wrap((int)floor(s) - msp + 1, Mr) / gt;
+            for (int j = 0; j < 4; ++j) {
+                const int tl = (first + j) & (ng - 1);
+                wt[8 * m + 4 * ax + (tl & 3)] = tile_start(s, tl * gt, Mr, msp, alpha);
+            }
+        }
+    }
+}
+
+bool weight_table_fits(const nlf_plan* p) {
+    // every tile a stencil overlaps has a slot (at most 4 along each axis: msp <= 12), the tile
+    // counts are multiples of 4 (slots agree across the periodic wrap), and tile_start() applies
+    return p->dim == 2 && p->msp <= 12 && p->Mr[0] % 32 == 0 && p->Mr[1] % 64 == 0 &&
+           p->Mr[0] >= 2 * p->msp + 8 && p->Mr[1] >= 2 * p->msp + 16;
+}
+
+int build_weight_table(nlf_plan* p) {
+    NLF_TRY(dev_alloc(p, &p->wtab, (size_t)p->Mh * 8 * sizeof(double2)));
+    dim3 grid((unsigned)std::min<long long>((p->Mh + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_weight_table, grid, dim3(256), 0, p->stream, p->s[0], p->s[1], p->Mh, p->Mr[0], p->Mr[1],
+                       p->msp, p->gc.alpha, reinterpret_cast<double2*>(p->wtab));
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
 }
 
 static size_t window_bytes(const nlf_plan* p) {
@@ -140,22 +177,37 @@ static int gather_spread_t(nlf_plan* p) {
     if constexpr (std::is_same<T, float>::value) {
         if (p->t1_prec != p->prec) {   // FP32 node values: FP32 matrix cores, FP64 spreading grid
             double2* g64 = reinterpret_cast<double2*>(p->grid_b);
-            if (p->dim == 2)
-                hipLaunchKernelGGL((k_mspread32<MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
-                                   c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+            if (p->dim == 2 && p->wtab && !BINS)   // explicit lists only, as for FP64 below
+                hipLaunchKernelGGL((k_mspread32<MSP, 2, KC, BINS, !BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64,
+                                   p->G, c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+            else if (p->dim == 2)
+                hipLaunchKernelGGL((k_mspread32<MSP, 2, KC, BINS, false>), ggrid, dim3(2 * KC), 0, p->stream, g64,
+                                   p->G, c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
             else
-                hipLaunchKernelGGL((k_mspread32<MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g64, p->G,
-                                   c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+                hipLaunchKernelGGL((k_mspread32<MSP, 3, KC, BINS, false>), ggrid, dim3(2 * KC), 0, p->stream, g64,
+                                   p->G, c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
             done = true;
         }
     }
     if (done) {
     } else if (p->dim == 2) {
-        hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
-                           na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+        // the table holds the tiles of the explicit lists (at most 4 per axis); the neighbour-bin
+        // streams also pass nodes of the bins next to those, which need the Gaussian's tail
+        constexpr bool kTab = MSP <= 12 && !BINS;   // the widths weight_table_fits() admits
+        bool launched = false;
+        if constexpr (kTab) {
+            if (p->wtab) {
+                hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC, BINS, true>), ggrid, dim3(2 * KC), 0, p->stream, g,
+                                   p->G, c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+                launched = true;
+            }
+        }
+        if (!launched)
+            hipLaunchKernelGGL((k_mspread<T, T, MSP, 2, KC, BINS, false>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G,
+                               c, p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
     } else {
-        hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, KC, BINS>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c, p->Mh,
-                           na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
+        hipLaunchKernelGGL((k_mspread<T, T, MSP, 3, KC, BINS, false>), ggrid, dim3(2 * KC), 0, p->stream, g, p->G, c,
+                           p->Mh, na, p->gitems, p->ngitems, p->gcand, qq, ba, pscr, sstride);
     }
     NLF_HIP(hipGetLastError());
     if (pscr) {

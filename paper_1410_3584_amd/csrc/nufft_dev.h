@@ -20,6 +20,11 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // index modulo an oversampled grid extent (always a power of two)
 __device__ __forceinline__ int wrap(int v, int M) { return v & (M - 1); }
 
+// Workgroup barrier for LDS traffic only: this wave's LDS operations have completed, then
+// s_barrier.  __syncthreads() also waits for every outstanding global load (its fence covers
+// global memory), which would drain loads issued ahead of the barrier for later blocks.
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Separable Gaussian weights for one axis: w[q] = exp(-alpha (q - msp + 1 - delta)^2), computed as
 // exp(-alpha delta^2) * exp(2 alpha delta)^p * exp(-alpha p^2) (Greengard-Lee fast gridding).
 template <typename T, int MSP>
@@ -62,6 +67,11 @@ struct NodeArgs {
     GaussConst gc;
     XcdSplit csplit;        // chunks over the XCDs (2D interpolation)
     XcdSplit isplit;        // gather work items over the XCDs (3D interpolation, spreading)
+    // 2D plans with a weight table (nlf_plan::wtab): per sorted node m, wtab[8 m + (t0 mod 4)] and
+    // wtab[8 m + 4 + (t1 mod 4)] hold tile_start() at the first cell of gather tile t0 along axis 0
+    // and t1 along axis 1, for the (at most 4 consecutive) tiles its stencil overlaps: the tiles
+    // whose explicit candidate lists hold the node
+    const double2* wtab;
 };
 
 struct EpiArgs {
@@ -352,19 +362,25 @@ __global__ void __launch_bounds__(kChunk) k_spread3(V2<T>* __restrict__ grid, lo
 // the node's 2 msp stencil keep their Gaussian weight instead of 0: it is below e^{-3 pi msp / 4},
 // the truncation level of the stencil itself.  Otherwise (small grids, where the stencil wraps onto
 // itself) the weight is the sum over the stencil offsets p == cell - l0 (mod Mr), p in [-msp+1, msp].
-template <int MSP, int GT>
-__device__ __forceinline__ void tile_weights(double s, int o, int Mr, double alpha, double qq, double (&w)[GT]) {
+// (g, r) of a node at cell o when Mr >= 2 msp + GT: the weight g = exp(-alpha x^2) at the cell's
+// offset x from the node and the ratio r = exp(-alpha (2 x + 1)) to the next cell.  The offset is
+// the representative in (msp - Mr, msp], which holds every offset a tile overlapping the stencil
+// can have (-msp - GT + 2 .. msp).
+__device__ __forceinline__ double2 tile_start(double s, int o, int Mr, int msp, double alpha) {
     const double f = floor(s);
     const int l0 = (int)f;
     const double d = s - f;
+    int p0 = wrap(o - l0 + msp - 1, Mr) - msp + 1;
+    if (p0 > msp) p0 -= Mr;
+    const double x = (double)p0 - d;
+    return make_double2(exp(-alpha * x * x), exp(-alpha * (2.0 * x + 1.0)));
+}
+
+template <int MSP, int GT>
+__device__ __forceinline__ void tile_weights(double s, int o, int Mr, double alpha, double qq, double (&w)[GT]) {
     if (Mr >= 2 * MSP + GT) {
-        // offset of cell o: the representative in (msp - Mr, msp], which holds every offset a tile
-        // overlapping the stencil can have (-msp - GT + 2 .. msp)
-        int p0 = wrap(o - l0 + MSP - 1, Mr) - MSP + 1;
-        if (p0 > MSP) p0 -= Mr;
-        double x = (double)p0 - d;
-        double g = exp(-alpha * x * x);
-        double r = exp(-alpha * (2.0 * x + 1.0));
+        const double2 gr = tile_start(s, o, Mr, MSP, alpha);
+        double g = gr.x, r = gr.y;
 #pragma unroll
         for (int k = 0; k < GT; ++k) {
             w[k] = g;
@@ -372,6 +388,9 @@ __device__ __forceinline__ void tile_weights(double s, int o, int Mr, double alp
             r *= qq;
         }
     } else {
+        const double f = floor(s);
+        const int l0 = (int)f;
+        const double d = s - f;
 #pragma unroll
         for (int k = 0; k < GT; ++k) {
             double acc = 0;
@@ -465,13 +484,14 @@ __host__ __device__ constexpr int mspread_lds() {
     return 2 * KC * 16 * (int)sizeof(double) + bin_table_lds<BINS>();
 }
 
-template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS>
+template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS, bool WT = false>
 __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long long gstride,
                                              const V2<T>* __restrict__ cbuf, long long cstride,
                                              const NodeArgs& na, const GItem* __restrict__ items, int nitems,
                                              const int* __restrict__ cand, double qq, const BinArgs& ba,
                                              double* __restrict__ pscr, long long sstride, VBlk vb,
                                              unsigned char* smem) {
+    static_assert(!WT || DIM == 2, "weight tables are 2D");
     constexpr int NW = 2 * KC / 64;   // waves; each multiplies KC / NW candidates of a block
     static_assert(KC % (4 * NW) == 0 && (KC / NW) % 8 == 0, "whole pairs of MFMA steps per wave");
     static_assert(2 * KC * 16 >= NW * 4 * 64, "wave partials fit S");
@@ -489,6 +509,8 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
     const int wv = t >> 6, lane = t & 63;
     const int r = lane & 15;
     const int kb = wv * (KC / NW);
+    // the weight-table slot of this thread's axis (A rows: axis 0, B rows: axis 1)
+    const int wslot = is_a ? (it.g0 & 3) : 4 + (it.g1 & 3);
     // four accumulators: independent product chains keep the FP64 matrix pipe busy
     d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
     // neighbour-bin streams: the tile's bin table (pref, start) in LDS
@@ -497,58 +519,97 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
     int* nb_start = nb_tmp + (kMaxNbrBins + 1);
     int nbn = 0;
     if (BINS) nbn = bin_table<2 * KC>(ba, it.g0, it.g1, it.g2, nb_pref, nb_tmp, nb_start);
-    // node data of this thread's candidate in the current block, loaded one block ahead so that
-    // the loads overlap the previous block's matrix products
-    double sa = 0.0, sb = 0.0;
-    V2<T> cv = mk2<T>((T)0, (T)0);
-    auto fetch = [&](int base) {
-        if (base + k < it.count) {
-            const int node = BINS ? bin_node(nb_pref, nb_start, nbn, (int)it.start + base + k)
-                                  : cand[it.start + base + k];
+    // Node data of this thread's candidate, loaded one block ahead so that the loads overlap the
+    // previous block's matrix products.
+    auto node_at = [&](int base) -> int {
+        if (WT) return cand[it.start + min(base + k, it.count - 1)];   // unconditional: see fetch
+        if (base + k >= it.count) return -1;
+        return BINS ? bin_node(nb_pref, nb_start, nbn, (int)it.start + base + k) : cand[it.start + base + k];
+    };
+    struct NodeData {
+        double sa, sb;
+        double2 wgr;   // WT: (g, r) of the candidate on this thread's tile axis
+        double m;      // WT: 1, or 0 past the item's count (zero rows)
+        V2<T> cv;
+    };
+    // WT: every lane loads, whether or not its candidate exists (past the count the last one
+    // stands in, multiplied by m = 0), and the B lanes load the node value too: unconditional
+    // loads, which the compiler's wait counts track exactly
+    auto fetch = [&](NodeData& d, int node, int base) {
+        if (WT) {
+            d.wgr = na.wtab[8 * (long long)node + wslot];
+            d.cv = cbuf[(long long)b * cstride + node];
+            d.m = (base + k < it.count) ? 1.0 : 0.0;
+            return;
+        }
+        if (node >= 0) {
             if (is_a) {
-                sa = na.s[0][node];
-                cv = cbuf[(long long)b * cstride + node];
-            } else {
-                sa = na.s[1][node];
-                if (DIM == 3) sb = na.s[2][node];
+                if (!WT) d.sa = na.s[0][node];
+                d.cv = cbuf[(long long)b * cstride + node];
+            } else if (!WT) {
+                d.sa = na.s[1][node];
+                if (DIM == 3) d.sb = na.s[2][node];
             }
         }
     };
-    fetch(0);
-    for (int base = 0; base < it.count; base += KC) {
+    NodeData d0{};
+    fetch(d0, node_at(0), 0);
+    auto block = [&](int base, NodeData& d) {
         const int cnt = min(KC, it.count - base);
-        if (base > 0) __syncthreads();   // the previous block's products have read S
+        if (base > 0) lds_barrier();   // the previous block's products have read S
         double row[16];
+        if (WT) {   // absent candidates have m = 0 (see fetch): no branch, no zeroing
+            double g = d.wgr.x * d.m, rr = d.wgr.y;
+            if (is_a) {
+                double gx = (double)d.cv.x * g, gy = (double)d.cv.y * g;
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    row[x] = gx;
+                    row[8 + x] = gy;
+                    gx *= rr;
+                    gy *= rr;
+                    rr *= qq;
+                }
+            } else {
+#pragma unroll
+                for (int y = 0; y < 16; ++y) {
+                    row[y] = g;
+                    g *= rr;
+                    rr *= qq;
+                }
+            }
+        } else {
 #pragma unroll
         for (int j = 0; j < 16; ++j) row[j] = 0.0;
         if (k < cnt) {
             if (is_a) {
                 double w0[8];
-                tile_weights<MSP, 8>(sa, o0, na.Mr[0], na.gc.alpha, qq, w0);
-                const double cx = (double)cv.x, cy = (double)cv.y;
+                tile_weights<MSP, 8>(d.sa, o0, na.Mr[0], na.gc.alpha, qq, w0);
+                const double cx = (double)d.cv.x, cy = (double)d.cv.y;
 #pragma unroll
                 for (int x = 0; x < 8; ++x) {
                     row[x] = cx * w0[x];
                     row[8 + x] = cy * w0[x];
                 }
             } else if (DIM == 2) {
-                tile_weights<MSP, 16>(sa, o1, na.Mr[1], na.gc.alpha, qq, row);
+                tile_weights<MSP, 16>(d.sa, o1, na.Mr[1], na.gc.alpha, qq, row);
             } else {
                 double w1[4], w2[4];
-                tile_weights<MSP, 4>(sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
-                tile_weights<MSP, 4>(sb, o2, na.Mr[2], na.gc.alpha, qq, w2);
+                tile_weights<MSP, 4>(d.sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
+                tile_weights<MSP, 4>(d.sb, o2, na.Mr[2], na.gc.alpha, qq, w2);
 #pragma unroll
                 for (int y = 0; y < 4; ++y)
 #pragma unroll
                     for (int z = 0; z < 4; ++z) row[4 * y + z] = w1[y] * w2[z];
             }
         }
+        }
         double* mine = S + (is_a ? 0 : KC * 16) + k * 16;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
             *reinterpret_cast<double2*>(mine + 2 * mrow_slot(k, c)) = make_double2(row[2 * c], row[2 * c + 1]);
-        __syncthreads();
-        fetch(base + KC);
+        lds_barrier();
+        fetch(d, node_at(base + KC), base + KC);   // the next block's (this block's weights are built)
         if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
             constexpr int kSteps = KC / NW / 4;
             double av[kSteps], bv[kSteps];
@@ -568,7 +629,8 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
                 acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 3], bv[q + 3], acc3, 0, 0, 0);
             }
         }
-    }
+    };
+    for (int base = 0; base < it.count; base += KC) block(base, d0);
     const d4_t acc = (acc0 + acc1) + (acc2 + acc3);
     __syncthreads();
 #pragma unroll
@@ -601,15 +663,15 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
     }
 }
 
-template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS>
+template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS, bool WT>
 __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
                                                         const int* __restrict__ cand, double qq, BinArgs ba,
                                                         double* __restrict__ pscr, long long sstride) {
     __shared__ __align__(16) unsigned char smem[mspread_lds<KC, BINS>()];
-    mspread_body<T, TG, MSP, DIM, KC, BINS>(grid, gstride, cbuf, cstride, na, items, nitems, cand, qq, ba, pscr,
-                                            sstride, hw_block(), smem);
+    mspread_body<T, TG, MSP, DIM, KC, BINS, WT>(grid, gstride, cbuf, cstride, na, items, nitems, cand, qq, ba, pscr,
+                                                sstride, hw_block(), smem);
 }
 
 // The same gather on the FP32 matrix cores, for FP32 plans (v_mfma_f32_16x16x4f32, twice the FP64
@@ -631,13 +693,14 @@ __host__ __device__ constexpr int mspread32_lds() {
            bin_table_lds<BINS>();
 }
 
-template <int MSP, int DIM, int KC, bool BINS>
+template <int MSP, int DIM, int KC, bool BINS, bool WT = false>
 __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long long gstride,
                                                const float2* __restrict__ cbuf, long long cstride,
                                                const NodeArgs& na, const GItem* __restrict__ items, int nitems,
                                                const int* __restrict__ cand, double qq, const BinArgs& ba,
                                                double* __restrict__ pscr, long long sstride, VBlk vb,
                                                unsigned char* smem) {
+    static_assert(!WT || DIM == 2, "weight tables are 2D");
     constexpr int NW = 2 * KC / 64;
     constexpr int KP = KC + 4;
     static_assert((KC / NW) % 16 == 0, "whole groups of four MFMA steps per wave");
@@ -657,39 +720,76 @@ __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long 
     const int wv = t >> 6, lane = t & 63;
     const int r = lane & 15, kq = lane >> 4;
     const int kb = wv * (KC / NW);
+    const int wslot = is_a ? (it.g0 & 3) : 4 + (it.g1 & 3);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int* nb_pref = reinterpret_cast<int*>(SB + 16 * KP);
     int* nb_tmp = nb_pref + (kMaxNbrBins + 1);
     int* nb_start = nb_tmp + (kMaxNbrBins + 1);
     int nbn = 0;
     if (BINS) nbn = bin_table<2 * KC>(ba, it.g0, it.g1, it.g2, nb_pref, nb_tmp, nb_start);
-    double sa = 0.0, sb = 0.0;
-    float2 cv = make_float2(0.0f, 0.0f);
-    auto fetch = [&](int base) {
-        if (base + k < it.count) {
-            const int node = BINS ? bin_node(nb_pref, nb_start, nbn, (int)it.start + base + k)
-                                  : cand[it.start + base + k];
+    // node data one block ahead, as in mspread_body
+    auto node_at = [&](int base) -> int {
+        if (WT) return cand[it.start + min(base + k, it.count - 1)];   // unconditional: see fetch
+        if (base + k >= it.count) return -1;
+        return BINS ? bin_node(nb_pref, nb_start, nbn, (int)it.start + base + k) : cand[it.start + base + k];
+    };
+    struct NodeData {
+        double sa, sb;
+        double2 wgr;
+        double m;
+        float2 cv;
+    };
+    auto fetch = [&](NodeData& d, int node, int base) {   // as in mspread_body
+        if (WT) {
+            d.wgr = na.wtab[8 * (long long)node + wslot];
+            d.cv = cbuf[(long long)b * cstride + node];
+            d.m = (base + k < it.count) ? 1.0 : 0.0;
+            return;
+        }
+        if (node >= 0) {
             if (is_a) {
-                sa = na.s[0][node];
-                cv = cbuf[(long long)b * cstride + node];
-            } else {
-                sa = na.s[1][node];
-                if (DIM == 3) sb = na.s[2][node];
+                if (!WT) d.sa = na.s[0][node];
+                d.cv = cbuf[(long long)b * cstride + node];
+            } else if (!WT) {
+                d.sa = na.s[1][node];
+                if (DIM == 3) d.sb = na.s[2][node];
             }
         }
     };
-    fetch(0);
-    for (int base = 0; base < it.count; base += KC) {
+    NodeData d0{};
+    fetch(d0, node_at(0), 0);
+    auto block = [&](int base, NodeData& d) {
         const int cnt = min(KC, it.count - base);
-        if (base > 0) __syncthreads();   // the previous block's products have read SA, SB
+        if (base > 0) lds_barrier();   // the previous block's products have read SA, SB
         float row[16];
+        if (WT) {   // absent candidates have m = 0 (see fetch): no branch, no zeroing
+            double g = d.wgr.x * d.m, rr = d.wgr.y;
+            if (is_a) {
+                double gx = (double)d.cv.x * g, gy = (double)d.cv.y * g;
+#pragma unroll
+                for (int x = 0; x < 8; ++x) {
+                    row[x] = (float)gx;
+                    row[8 + x] = (float)gy;
+                    gx *= rr;
+                    gy *= rr;
+                    rr *= qq;
+                }
+            } else {
+#pragma unroll
+                for (int y = 0; y < 16; ++y) {
+                    row[y] = (float)g;
+                    g *= rr;
+                    rr *= qq;
+                }
+            }
+        } else {
 #pragma unroll
         for (int j = 0; j < 16; ++j) row[j] = 0.0f;
         if (k < cnt) {
             if (is_a) {
                 double w0[8];
-                tile_weights<MSP, 8>(sa, o0, na.Mr[0], na.gc.alpha, qq, w0);
-                const double cx = (double)cv.x, cy = (double)cv.y;
+                tile_weights<MSP, 8>(d.sa, o0, na.Mr[0], na.gc.alpha, qq, w0);
+                const double cx = (double)d.cv.x, cy = (double)d.cv.y;
 #pragma unroll
                 for (int x = 0; x < 8; ++x) {
                     row[x] = (float)(cx * w0[x]);
@@ -697,24 +797,25 @@ __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long 
                 }
             } else if (DIM == 2) {
                 double w1[16];
-                tile_weights<MSP, 16>(sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
+                tile_weights<MSP, 16>(d.sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
 #pragma unroll
                 for (int j = 0; j < 16; ++j) row[j] = (float)w1[j];
             } else {
                 double w1[4], w2[4];
-                tile_weights<MSP, 4>(sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
-                tile_weights<MSP, 4>(sb, o2, na.Mr[2], na.gc.alpha, qq, w2);
+                tile_weights<MSP, 4>(d.sa, o1, na.Mr[1], na.gc.alpha, qq, w1);
+                tile_weights<MSP, 4>(d.sb, o2, na.Mr[2], na.gc.alpha, qq, w2);
 #pragma unroll
                 for (int y = 0; y < 4; ++y)
 #pragma unroll
                     for (int z = 0; z < 4; ++z) row[4 * y + z] = (float)(w1[y] * w2[z]);
             }
         }
+        }
         float* dst = is_a ? SA : SB;
 #pragma unroll
         for (int j = 0; j < 16; ++j) dst[j * KP + k] = row[j];
-        __syncthreads();
-        fetch(base + KC);
+        lds_barrier();
+        fetch(d, node_at(base + KC), base + KC);   // the next block's (this block's weights are built)
         if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
             constexpr int kSteps = KC / NW / 4;
             f4_t c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0, c2 = c0, c3 = c0;
@@ -729,7 +830,8 @@ __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long 
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[v] += (double)((c0[v] + c1[v]) + (c2[v] + c3[v]));
         }
-    }
+    };
+    for (int base = 0; base < it.count; base += KC) block(base, d0);
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) R[(wv * 4 + v) * 64 + lane] = acc[v];
@@ -759,15 +861,15 @@ __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long 
     }
 }
 
-template <int MSP, int DIM, int KC, bool BINS>
+template <int MSP, int DIM, int KC, bool BINS, bool WT>
 __global__ void __launch_bounds__(2 * KC, 4) k_mspread32(double2* __restrict__ grid, long long gstride,
                                                           const float2* __restrict__ cbuf, long long cstride,
                                                           NodeArgs na, const GItem* __restrict__ items, int nitems,
                                                           const int* __restrict__ cand, double qq, BinArgs ba,
                                                           double* __restrict__ pscr, long long sstride) {
     __shared__ __align__(16) unsigned char smem[mspread32_lds<KC, BINS>()];
-    mspread32_body<MSP, DIM, KC, BINS>(grid, gstride, cbuf, cstride, na, items, nitems, cand, qq, ba, pscr, sstride,
-                                       hw_block(), smem);
+    mspread32_body<MSP, DIM, KC, BINS, WT>(grid, gstride, cbuf, cstride, na, items, nitems, cand, qq, ba, pscr, sstride,
+                                           hw_block(), smem);
 }
 
 // Deterministic plans: a tile of several work items adds its items' partial sums in slot order

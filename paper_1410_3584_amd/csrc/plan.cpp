@@ -743,6 +743,8 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     NLF_TRY(dev_alloc(p, &p->cbuf, (size_t)p->batch * Mh * es));
     if (p->use_gather && p->dim == 3) NLF_TRY(dev_alloc(p, (void**)&p->iacc, (size_t)p->batch * Mh * 2 * sizeof(double)));
     for (int i = 0; i < p->dim; ++i) NLF_TRY(upload(p, (void**)&p->s[i], ss[i].data(), Mh * sizeof(double)));
+    // the spreading's per-node tile weights (128 bytes per node): the node positions are fixed
+    if ((p->use_gather || p->gather_impl_ok) && weight_table_fits(p)) NLF_TRY(build_weight_table(p));
     NLF_TRY(upload(p, (void**)&p->wfac, wf.data(), Mh * sizeof(double)));
     if (kernel == NLF_LAPLACE2D) NLF_TRY(upload(p, (void**)&p->gk, gk.data(), Mh * sizeof(double)));
     NLF_TRY(upload(p, (void**)&p->perm, order.data(), Mh * sizeof(int)));
