@@ -107,19 +107,23 @@ template <bool PAD>
 __device__ __forceinline__ int lpad(int e) { return PAD ? e + (e >> 3) : e; }
 __host__ __device__ __forceinline__ int lds_line(int n, bool pad) { return pad ? n + (n >> 3) : n; }
 
+// All sizes are powers of two (lg = log2 n, lgp = log2 p): indices by shifts and masks.
 template <typename T, int DIR, int NT, int E, int R, bool HALF, bool PAD>
-__device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, int p, const V2<T>* __restrict__ tw) {
+__device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int lg, int nl, int p, int lgp,
+                                         const V2<T>* __restrict__ tw) {
     constexpr int RB = (E + R * NT - 1) / (R * NT);   // butterflies per thread
-    const int q = n / R;
-    const int tot = nl * q;
-    const int tstep = n / (R * p);
+    constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : 3);
+    const int lq = lg - LR;                            // q = n / R
+    const int q = 1 << lq;
+    const int tot = nl << lq;
+    const int lts = lq - lgp;                          // tstep = n / (R p)
     const int tid = threadIdx.x;
     V2<T> y[RB][R];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
         const int idx = tid + r * NT;
         if (idx < tot) {
-            const int line = idx / q, i = idx - line * q;
+            const int line = idx >> lq, i = idx & (q - 1);
             const int k = i & (p - 1);
             const V2<T>* x = buf + line * pitch;
 #pragma unroll
@@ -127,7 +131,7 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
             if (p > 1) {
 #pragma unroll
                 for (int m = 1; m < R; ++m) {
-                    const int tt = m * k * tstep;
+                    const int tt = (m * k) << lts;
                     V2<T> w;
                     if constexpr (HALF) {   // half table (in LDS): w^(t + n/2) = -w^t
                         w = tw[tt < (n >> 1) ? tt : tt - (n >> 1)];
@@ -156,7 +160,7 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
     for (int r = 0; r < RB; ++r) {
         const int idx = tid + r * NT;
         if (idx < tot) {
-            const int line = idx / q, i = idx - line * q;
+            const int line = idx >> lq, i = idx & (q - 1);
             const int k = i & (p - 1);
             const int j = (i - k) * R + k;
             V2<T>* x = buf + line * pitch;
@@ -170,17 +174,20 @@ __device__ __forceinline__ void fft_pass(V2<T>* buf, int pitch, int n, int nl, i
 // HALF: tw holds w^t for t < n/2 only (the LDS copy); otherwise the full table
 template <typename T, int DIR, int NT, int E, bool HALF = false, bool PAD = HALF>
 __device__ void lds_fft(V2<T>* buf, int pitch, int n, int lg, int nl, const V2<T>* __restrict__ tw) {
-    int p = 1;
+    int p = 1, lgp = 0;
     if (lg % 3 == 1) {
-        fft_pass<T, DIR, NT, E, 2, HALF, PAD>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 2, HALF, PAD>(buf, pitch, n, lg, nl, p, lgp, tw);
         p = 2;
+        lgp = 1;
     } else if (lg % 3 == 2) {
-        fft_pass<T, DIR, NT, E, 4, HALF, PAD>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 4, HALF, PAD>(buf, pitch, n, lg, nl, p, lgp, tw);
         p = 4;
+        lgp = 2;
     }
     while (p < n) {
-        fft_pass<T, DIR, NT, E, 8, HALF, PAD>(buf, pitch, n, nl, p, tw);
+        fft_pass<T, DIR, NT, E, 8, HALF, PAD>(buf, pitch, n, lg, nl, p, lgp, tw);
         p *= 8;
+        lgp += 3;
     }
 }
 
@@ -283,7 +290,7 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
             rv[u] = 0.0;
             dv[u] = 0.0;
             if (idx < nl * n) {
-                const int l = idx / n, c = idx - l * n;
+                const int l = idx >> a.lg, c = idx & (n - 1);
                 // oversampled position c holds data index j with dmap(j) == c, if any
                 if (is_data_row(c, ndl, n)) {
                     const int j = (c < ndl / 2) ? c + ndl / 2 : c - (n - ndl / 2);
@@ -302,7 +309,7 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
         for (int u = 0; u < PER; ++u) {
             const int idx = threadIdx.x + u * NT;
             if (idx < nl * n) {
-                const int l = idx / n, c = idx - l * n;
+                const int l = idx >> a.lg, c = idx & (n - 1);
                 double fac = 1;
                 int j0 = 0, j1 = 0;
                 (void)grid_line(l, &fac, &j0, &j1);
@@ -339,7 +346,7 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
             const int idx = threadIdx.x + u * NT;
             v[u] = mk<T>(0, 0);
             if (idx < nl * n) {
-                const int l = idx / n, c = idx - l * n;
+                const int l = idx >> a.lg, c = idx & (n - 1);
                 double fac;
                 int j0, j1;
                 const long long gl = grid_line(l, &fac, &j0, &j1);
@@ -355,7 +362,7 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int idx = threadIdx.x + u * NT;
-            if (idx < nl * n) buf[(idx / n) * pitch + idx % n] = v[u];
+            if (idx < nl * n) buf[(idx >> a.lg) * pitch + (idx & (n - 1))] = v[u];
         }
     }
 #pragma unroll
@@ -377,7 +384,7 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
         }
     } else if (STORE == STORE_GRID) {
         for (int idx = threadIdx.x; idx < nl * n; idx += NT) {
-            int l = idx / n, c = idx - l * n;
+            int l = idx >> a.lg, c = idx & (n - 1);
             double fac;
             int j0, j1;
             long long gl = grid_line(l, &fac, &j0, &j1);
@@ -392,8 +399,9 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
             m1y = a.mom[4 * b + 2];
         }
         const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
+        const int lgd = __builtin_ctz(ndl);   // the data length is a power of two (half the line)
         for (int idx = threadIdx.x; idx < nl * ndl; idx += NT) {
-            int l = idx / ndl, j = idx - l * ndl;
+            int l = idx >> lgd, j = idx & (ndl - 1);
             double fac;
             int j0, j1;
             (void)grid_line(l, &fac, &j0, &j1);
@@ -458,7 +466,7 @@ __device__ __forceinline__ long long band_col(const ColsArgs& a, int cb) {
 template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E, bool TWL>
 __device__ __forceinline__ void fft_cols_body(const ColsArgs& a, VBlk vb, unsigned char* smem_raw) {
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    const int n = a.n, C = a.C;
+    const int n = a.n, C = a.C, lgC = __builtin_ctz(C);   // C is a power of two
     const int pitch = lds_line(n, TWL) + 1;
     if (a.mom && vb.x == 0 && vb.y == 0) {   // uniform over the workgroup
         __shared__ double red16[16];
@@ -494,7 +502,7 @@ __device__ __forceinline__ void fft_cols_body(const ColsArgs& a, VBlk vb, unsign
         const int idx = threadIdx.x + u * NT;
         v[u] = mk<T>(0, 0);
         if (idx < n * C) {
-            const int r = idx / C, c = idx - r * C;
+            const int r = idx >> lgC, c = idx & (C - 1);
             if (!LPRUNE || is_data_row(r, a.nd, n)) v[u] = base[(long long)r * a.inner + c];
         }
         if (TWL && idx < (n >> 1)) tv[u] = reinterpret_cast<const V2<T>*>(a.tw)[idx];
@@ -502,14 +510,14 @@ __device__ __forceinline__ void fft_cols_body(const ColsArgs& a, VBlk vb, unsign
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
-        if (idx < n * C) buf[(idx % C) * pitch + lpad<TWL>(idx / C)] = v[u];
+        if (idx < n * C) buf[(idx & (C - 1)) * pitch + lpad<TWL>(idx >> lgC)] = v[u];
         if (TWL && idx < (n >> 1)) twl[idx] = tv[u];
     }
     __syncthreads();
     lds_fft<T, DIR, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     const int nds = a.nd_store > 0 ? a.nd_store : a.nd;
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
-        int r = idx / C, c = idx - r * C;
+        int r = idx >> lgC, c = idx & (C - 1);
         if (!SPRUNE || is_data_row(r, nds, n)) base[(long long)r * a.inner + c] = buf[c * pitch + lpad<TWL>(r)];
     }
 }
@@ -532,9 +540,10 @@ struct ConvW {
 
 template <typename T, int NT, int E, bool TWL>
 __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
+    static_assert(NT % 16 == 0, "a thread keeps one of the C <= 16 columns");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    const int n = a.n, C = a.C;
+    const int n = a.n, C = a.C, lgC = __builtin_ctz(C);   // C is a power of two
     const int pitch = lds_line(n, TWL) + 1;
     int cb = blockIdx.x;
     const int nb = gridDim.x;
@@ -549,7 +558,7 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
         const int idx = threadIdx.x + u * NT;
         v[u] = mk<T>(0, 0);
         if (idx < n * C) {
-            const int r = idx / C, c = idx - r * C;
+            const int r = idx >> lgC, c = idx & (C - 1);
             if (is_data_row(r, a.nd, n)) v[u] = base[(long long)r * a.inner + c];
         }
         if (TWL && idx < (n >> 1)) tv[u] = reinterpret_cast<const V2<T>*>(a.tw)[idx];
@@ -557,21 +566,29 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int idx = threadIdx.x + u * NT;
-        if (idx < n * C) buf[(idx % C) * pitch + lpad<TWL>(idx / C)] = v[u];
+        if (idx < n * C) buf[(idx & (C - 1)) * pitch + lpad<TWL>(idx >> lgC)] = v[u];
         if (TWL && idx < (n >> 1)) twl[idx] = tv[u];
     }
     __syncthreads();
     lds_fft<T, -1, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     __syncthreads();
+    // a thread keeps one column (NT is a multiple of C): its (k1, k2) part once, and
+    // e^{-|k|^2/a} = e^{-k0^2/a} e^{-(k1^2 + k2^2)/a}; near k = 0, where 1 - e^{-x} cancels, expm1
+    const int c = threadIdx.x & (C - 1);
+    const long long col = col0 + c;
+    const int c1 = (int)(col / cw.pitch2), c2 = (int)(col - (long long)c1 * cw.pitch2);
+    const double k1 = (c1 < cw.Mr1 / 2 ? c1 : c1 - cw.Mr1) * cw.dk1;
+    const double k2 = (c2 < cw.Mr2 / 2 ? c2 : c2 - cw.Mr2) * cw.dk2;
+    const double q12 = k1 * k1 + k2 * k2;
+    const double e12 = exp(-q12 * cw.inva);
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
-        int r = idx / C, c = idx - r * C;
-        const long long col = col0 + c;
-        const int c1 = (int)(col / cw.pitch2), c2 = (int)(col - (long long)c1 * cw.pitch2);
+        const int r = idx >> lgC;
         const double k0 = (r < cw.Mr0 / 2 ? r : r - cw.Mr0) * cw.dk0;
-        const double k1 = (c1 < cw.Mr1 / 2 ? c1 : c1 - cw.Mr1) * cw.dk1;
-        const double k2 = (c2 < cw.Mr2 / 2 ? c2 : c2 - cw.Mr2) * cw.dk2;
-        const double kk = k0 * k0 + k1 * k1 + k2 * k2;
-        const double w = kk > 0.0 ? -expm1(-kk * cw.inva) / kk : cw.inva;
+        const double kk = k0 * k0 + q12;
+        const double x = kk * cw.inva;
+        double w;
+        if (x >= 1.0) w = (1.0 - exp(-k0 * k0 * cw.inva) * e12) / kk;
+        else w = kk > 0.0 ? -expm1(-x) / kk : cw.inva;
         V2<T> v = buf[c * pitch + lpad<TWL>(r)];
         v.x = (T)((double)v.x * w);
         v.y = (T)((double)v.y * w);
@@ -581,7 +598,7 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
     lds_fft<T, 1, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     __syncthreads();
     for (int idx = threadIdx.x; idx < n * C; idx += NT) {
-        int r = idx / C, c = idx - r * C;
+        int r = idx >> lgC, c = idx & (C - 1);
         if (is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + lpad<TWL>(r)];
     }
 }
