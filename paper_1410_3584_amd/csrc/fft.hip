@@ -72,9 +72,8 @@ static constexpr int cols_kind() {
     return -1;
 }
 
-template <typename T, int DIR, int LOAD, int STORE, typename TIO, int E, bool TWL>
+template <typename T, int DIR, int LOAD, int STORE, typename TIO, int E, bool TWL, int NT = RowCfg::NT>
 static int launch_rows_cfg(nlf_plan* p, RowsArgs a, int batch) {
-    constexpr int NT = RowCfg::NT;
     a.lg = ilog2(a.n);
     a.lines_per_wg = std::max(1, E / a.n);
     if (a.n > E) return set_error(NLF_EUNSUPPORTED, "FFT length %d exceeds the LDS line budget", a.n);
@@ -94,26 +93,27 @@ static int launch_rows_cfg(nlf_plan* p, RowsArgs a, int batch) {
     {
         std::lock_guard<std::mutex> lock(attr_mu);
         if (lds > attr_bytes) {
-            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>,
+            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL, NT>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             attr_bytes = lds;
         }
     }
-    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL>), grid, dim3(NT), lds, p->stream, a);
+    hipLaunchKernelGGL((k_fft_rows<T, TIO, DIR, LOAD, STORE, E, TWL, NT>), grid, dim3(NT), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
 
 // LDS element budget of the contiguous-axis kernel for lines of length n: 1024-point lines get
 // one line per workgroup (twice the workgroups of the 2048-element budget)
-static int rows_budget(int n) { return n == 1024 ? 1024 : RowCfg::E; }
+static int rows_budget(int n) { return n == 1024 ? Row1024Cfg::E : RowCfg::E; }
 static int rows_lines_per_wg(int n) { return std::max(1, rows_budget(n) / n); }
 
 template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
 static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, ExecRowCfg::E, true>(p, a, batch);
-    if (rows_budget(a.n) == 1024) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, 1024, false>(p, a, batch);
+    if (a.n == 1024)
+        return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, Row1024Cfg::E, Row1024Cfg::TWL, Row1024Cfg::NT>(p, a, batch);
     if (a.n <= 512) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, true>(p, a, batch);
     return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, false>(p, a, batch);
 }
@@ -166,6 +166,8 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
         return launch_cols_cfg<T, DIR, LP, SP, ExecColCfg::NT, ExecColCfg::E, true>(p, a, outer, batch);
     if (a.n <= 512)
         return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E, true>(p, a, outer, batch);
+    if (a.n == 1024)
+        return launch_cols_cfg<T, DIR, LP, SP, Col1024Cfg::NT, Col1024Cfg::E, Col1024Cfg::TWL>(p, a, outer, batch);
     return launch_cols_cfg<T, DIR, LP, SP, FftCfg<T>::NT, FftCfg<T>::E, false>(p, a, outer, batch);
 }
 

@@ -37,6 +37,13 @@ struct ColSmallCfg { static constexpr int E = 4096, NT = 1024; };
 // element budgets that give each thread as many elements as the kernels' own configurations.
 struct ExecRowCfg { static constexpr int E = 1024, NT = 256; };
 struct ExecColCfg { static constexpr int E = 1024, NT = 256; };
+// 1024-point lines (the oversampled axes of the 512^2 grids).  Measured at 512^2 (FP64 evaluation,
+// forward + inverse FFT stages, us): these shapes 26.7 + 23.3; rows of 128 or 1024 threads per
+// line 27.4-32.9 + 25.3-26.6 (a pass has 128 radix-8 butterflies per line, but the 512 line
+// workgroups then hold too few waves per CU to cover the loads); twiddles in LDS 27.4 + 25.0;
+// column blocks of 2 columns (256 threads) or of 4 with 1024 threads 27.3-27.9 + 25.2-27.0.
+struct Row1024Cfg { static constexpr int E = 1024, NT = 512; static constexpr bool TWL = false; };
+struct Col1024Cfg { static constexpr int E = 8192, NT = 512; static constexpr bool TWL = false; };
 
 // data index j (0..nd-1, x_j = -L + j h) -> row of the 2x oversampled periodic grid holding
 // centred frequency/position j - nd/2
@@ -421,10 +428,10 @@ __device__ __forceinline__ void fft_rows_body(const RowsArgs& a, VBlk vb, unsign
     }
 }
 
-template <typename T, typename TIO, int DIR, int LOAD, int STORE, int E, bool TWL>
-__global__ void __launch_bounds__(RowCfg::NT) k_fft_rows(RowsArgs a) {
+template <typename T, typename TIO, int DIR, int LOAD, int STORE, int E, bool TWL, int NT = RowCfg::NT>
+__global__ void __launch_bounds__(NT) k_fft_rows(RowsArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fft_rows_body<T, TIO, DIR, LOAD, STORE, E, TWL, RowCfg::NT>(a, hw_block(), smem_raw);
+    fft_rows_body<T, TIO, DIR, LOAD, STORE, E, TWL, NT>(a, hw_block(), smem_raw);
 }
 
 // ---- strided-axis kernel ----------------------------------------------------------------------
@@ -589,16 +596,16 @@ __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {
         double w;
         if (x >= 1.0) w = (1.0 - exp(-k0 * k0 * cw.inva) * e12) / kk;
         else w = kk > 0.0 ? -expm1(-x) / kk : cw.inva;
-        V2<T> v = buf[c * pitch + lpad<TWL>(r)];
-        v.x = (T)((double)v.x * w);
-        v.y = (T)((double)v.y * w);
-        buf[c * pitch + lpad<TWL>(r)] = v;
+        V2<T> e = buf[c * pitch + lpad<TWL>(r)];
+        e.x = (T)((double)e.x * w);
+        e.y = (T)((double)e.y * w);
+        buf[c * pitch + lpad<TWL>(r)] = e;
     }
     __syncthreads();
     lds_fft<T, 1, NT, E, TWL>(buf, pitch, n, a.lg, C, TWL ? twl : reinterpret_cast<const V2<T>*>(a.tw));
     __syncthreads();
-    for (int idx = threadIdx.x; idx < n * C; idx += NT) {
-        int r = idx >> lgC, c = idx & (C - 1);
+    for (int idx = threadIdx.x; idx < n * C; idx += NT) {   // column c of this thread, as above
+        const int r = idx >> lgC;
         if (is_data_row(r, a.nd, n)) base[(long long)r * a.inner + c] = buf[c * pitch + lpad<TWL>(r)];
     }
 }

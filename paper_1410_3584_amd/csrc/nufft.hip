@@ -42,6 +42,7 @@ static NodeArgs node_args(const nlf_plan* p) {
     na.csplit = p->chunk_split;
     na.isplit = p->item_split;
     na.wtab = reinterpret_cast<const double2*>(p->wtab);
+    na.itab = reinterpret_cast<const double2*>(p->itab);
     return na;
 }
 
@@ -62,6 +63,50 @@ __global__ void k_weight_table(const double* __restrict__ s0, const double* __re
                 wt[8 * m + 4 * ax + (tl & 3)] = tile_start(s, tl * gt, Mr, msp, alpha);
             }
         }
+    }
+}
+
+// The interpolation table of a 2D FP64 plan (see NodeArgs::itab), one workgroup per chunk: node t
+// of a chunk belongs to the group of 16 starting at t - t mod 16 (k_binterp2's wave groups).
+template <int MSP>
+__global__ void k_interp_table(const Chunk* __restrict__ chunks, const double* __restrict__ s0,
+                               const double* __restrict__ s1, int Mr0, int Mr1, double alpha, double2* __restrict__ it) {
+    const Chunk ch = chunks[blockIdx.x];
+    const int t = threadIdx.x;
+    if (t >= ch.count) return;
+    const int node = ch.start + t, first = ch.start + (t & ~15);
+    const double f0 = floor(s0[node]), f1 = floor(s1[node]);
+    const int rx0 = wrap((int)f0, Mr0) - ch.t0 * 8, ry0 = wrap((int)f1, Mr1) - ch.t1 * 16;
+    const int c0 = wrap((int)floor(s1[first]), Mr1) - ch.t1 * 16;
+    for (int ka = 0; ka < 4; ++ka) {
+        double2 wy, wx;
+        binterp2_starts<MSP>(s0[node] - f0, s1[node] - f1, rx0, ry0, c0, ka, alpha, wy, wx);
+        it[2 * (4 * (long long)node + ka)] = wy;
+        it[2 * (4 * (long long)node + ka) + 1] = wx;
+    }
+}
+
+template <int MSP>
+static int interp_table_t(nlf_plan* p) {
+    NLF_TRY(dev_alloc(p, &p->itab, (size_t)p->Mh * 8 * sizeof(double2)));
+    hipLaunchKernelGGL((k_interp_table<MSP>), dim3(p->nchunks), dim3(kChunk), 0, p->stream, p->chunks, p->s[0], p->s[1],
+                       p->Mr[0], p->Mr[1], p->gc.alpha, reinterpret_cast<double2*>(p->itab));
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+int build_interp_table(nlf_plan* p) {
+    if (p->dim != 2 || p->prec != NLF_F64 || p->nchunks == 0) return NLF_OK;
+    switch (p->msp) {
+        case 8: return interp_table_t<8>(p);
+        case 9: return interp_table_t<9>(p);
+        case 10: return interp_table_t<10>(p);
+        case 11: return interp_table_t<11>(p);
+        case 12: return interp_table_t<12>(p);
+        case 13: return interp_table_t<13>(p);
+        case 14: return interp_table_t<14>(p);
+        case 16: return interp_table_t<16>(p);
+        default: return NLF_OK;
     }
 }
 
@@ -109,8 +154,12 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
             hipLaunchKernelGGL((k_binterp2_32<MSP>), grid, dim3(256), 0, p->stream,
                                reinterpret_cast<const float2*>(p->grid_a), p->G, na, ea, qq4, exp(-2.0 * p->gc.alpha),
                                zb, (long long)(bbytes / 16));
+        } else if (p->itab) {
+            hipLaunchKernelGGL((k_binterp2<T, MSP, true>), grid, dim3(256), 0, p->stream,
+                               reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4, zb,
+                               (long long)(bbytes / 16));
         } else {
-            hipLaunchKernelGGL((k_binterp2<T, MSP>), grid, dim3(256), 0, p->stream,
+            hipLaunchKernelGGL((k_binterp2<T, MSP, false>), grid, dim3(256), 0, p->stream,
                                reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4, zb,
                                (long long)(bbytes / 16));
         }

@@ -72,6 +72,10 @@ struct NodeArgs {
     // and t1 along axis 1, for the (at most 4 consecutive) tiles its stencil overlaps: the tiles
     // whose explicit candidate lists hold the node
     const double2* wtab;
+    // 2D FP64 plans (nlf_plan::itab): per sorted node m and lane quarter ka = 0..3 of the per-bin
+    // interpolation, itab[2 (4 m + ka)] = (g, r) of its y-weights and itab[2 (4 m + ka) + 1] of
+    // its x-weights: the start values of the step-4 recurrences of k_binterp2
+    const double2* itab;
 };
 
 struct EpiArgs {
@@ -926,7 +930,19 @@ struct Binterp2Lds {
                                  kChunk * 2 * (int)sizeof(int);
 };
 
-template <typename T, int MSP>
+// Start values of lane quarter ka's y-weight (columns c0 + 4 st + ka) and x-weight (rows 4 m + ka)
+// recurrences for a node with fractional parts (d0, d1) and bin offsets (rx0, ry0) in a group whose
+// first node has column offset c0: g = exp(-alpha x^2) at the first offset x, r = exp(-alpha (8 x + 16)).
+template <int MSP>
+__device__ __forceinline__ void binterp2_starts(double d0, double d1, int rx0, int ry0, int c0, int ka, double alpha,
+                                                double2& wy, double2& wx) {
+    const double y0 = (double)(c0 + ka - ry0 - (MSP - 1)) - d1;
+    wy = make_double2(exp(-alpha * y0 * y0), exp(-alpha * (8.0 * y0 + 16.0)));
+    const double x0 = (double)(ka - rx0 - (MSP - 1)) - d0;
+    wx = make_double2(exp(-alpha * x0 * x0), exp(-alpha * (8.0 * x0 + 16.0)));
+}
+
+template <typename T, int MSP, bool ITAB = false>
 __device__ __forceinline__ void binterp2_body(const V2<T>* __restrict__ grid, long long gstride, const NodeArgs& na,
                                               const EpiArgs& ea, double qq4, double2* __restrict__ zero,
                                               long long zero16, VBlk vb, unsigned char* smem) {
@@ -995,12 +1011,18 @@ __device__ __forceinline__ void binterp2_body(const V2<T>* __restrict__ grid, lo
         const int ksg = (c1 - c0 + 2 * MSP + 3) >> 2;   // k-steps this group needs (<= KS)
         double bv[KS], wx[2 * RBX];
         if (jn < ch.count) {
-            const double d0 = nd[jn][0], d1 = nd[jn][1];
             const int rx0 = noff[jn][0], ry0 = noff[jn][1];
+            double2 sy, sx;   // start values of the y- and x-weight recurrences
+            if (ITAB) {   // the plan's table of these start values (fixed node positions)
+                const double2* it2 = na.itab + 2 * (4 * (long long)(ch.start + jn) + ka);
+                sy = it2[0];
+                sx = it2[1];
+            } else {
+                binterp2_starts<MSP>(nd[jn][0], nd[jn][1], rx0, ry0, c0, ka, alpha, sy, sx);
+            }
             {   // y-weights of columns c0 + 4 st + ka: stencil offset q = c0 + 4 st + ka - ry0 in [0, 2 msp)
                 const int q0 = c0 + ka - ry0;
-                const double x0 = (double)(q0 - (MSP - 1)) - d1;
-                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
+                double gg = sy.x, rr = sy.y;
 #pragma unroll
                 for (int st = 0; st < KS; ++st) {
                     const int q = q0 + 4 * st;
@@ -1011,8 +1033,7 @@ __device__ __forceinline__ void binterp2_body(const V2<T>* __restrict__ grid, lo
             }
             {   // x-weights of rows 4 m + ka
                 const int q0 = ka - rx0;
-                const double x0 = (double)(q0 - (MSP - 1)) - d0;
-                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
+                double gg = sx.x, rr = sx.y;
 #pragma unroll
                 for (int m = 0; m < 2 * RBX; ++m) {
                     const int q = q0 + 4 * m;
@@ -1059,12 +1080,12 @@ __device__ __forceinline__ void binterp2_body(const V2<T>* __restrict__ grid, lo
     }
 }
 
-template <typename T, int MSP>
+template <typename T, int MSP, bool ITAB>
 __global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
                                                  NodeArgs na, EpiArgs ea, double qq4,
                                                  double2* __restrict__ zero, long long zero16) {
     __shared__ __align__(16) unsigned char smem[Binterp2Lds<MSP>::bytes];
-    binterp2_body<T, MSP>(grid, gstride, na, ea, qq4, zero, zero16, hw_block(), smem);
+    binterp2_body<T, MSP, ITAB>(grid, gstride, na, ea, qq4, zero, zero16, hw_block(), smem);
 }
 
 // The same per-bin interpolation on the FP32 matrix cores for FP32 plans: the window planes in LDS
