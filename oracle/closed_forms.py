@@ -41,7 +41,8 @@ def coulomb3d_gauss(r, sigma):
 
 
 def coulomb3d_gauss_aniso(x, y, z, sigma, gamma):
-    """Example 2.1, gamma != 1 branch: a 1D integral evaluated by adaptive quadrature."""
+    """Example 2.1, gamma != 1 branch: a 1D integral evaluated by adaptive quadrature (tested at
+    gamma = 1 against the erf formula and at gamma = 2 against the split evaluation)."""
     g2 = gamma ** -2
 
     def one(xx, yy, zz):

@@ -1,6 +1,6 @@
 // Hand-written Stockham FFT for gfx950, used on the 2x-oversampled NUFFT grid and on the
-// solver grid.  One workgroup transforms a block of lines held in LDS (radix-4 passes plus one
-// radix-2 pass for odd log2 n).  Two kernels:
+// solver grid.  One workgroup transforms a block of lines held in LDS (radix-8 passes, after one
+// radix-2 or radix-4 pass when log2 n is not a multiple of 3).  Two kernels:
 //   k_fft_rows : lines along the contiguous (last) axis.  Optional fused prologue/epilogue:
 //                real density in -> precorrect (divide by the Gaussian's Fourier coefficients)
 //                and zero-pad into the oversampled line (type-2 NUFFT input), and

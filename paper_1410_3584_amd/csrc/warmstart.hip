@@ -1,7 +1,8 @@
 // Learned warm start for the gradient flow (a project addition, not in the paper): a small FP32
 // MLP maps the physical parameters of a field, (ln beta, gamma_0, gamma_1[, gamma_2]), to its ground
-// state on a coarse grid of the same box; the prediction is interpolated trilinearly (bilinearly in
-// 2D) to the plan's grid and normalised, and serves as the initial guess of the flow of Sec. 3.1.
+// state on a coarse grid of the same box; the prediction is resampled to the plan's grid by
+// band-limited (periodic Dirichlet) interpolation along each axis and normalised, and serves as the
+// initial guess of the flow of Sec. 3.1.
 // Everything -- forward, backward, loss, Adam -- runs in the kernels below.
 //
 // Network: x (n_in) -> tanh(W1 x + b1) (H) -> tanh(W2 . + b2) (H) -> W3 . + b3 (n_out).

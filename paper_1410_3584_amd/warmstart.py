@@ -3,8 +3,9 @@ solver, training with the library's own network kernels, and the warm-vs-Gaussia
 All numerical work runs in libnlf.so (nlf_ground_state*, nlf_ws_*); this module only arranges
 the calls and the bookkeeping.
 
-    python -m paper_1410_3584_amd.warmstart --dim 3 --n 64 --coarse 32 --train 2000 --test 200
-prints one JSON line with the held-out comparison.
+    python -m paper_1410_3584_amd.warmstart --dim 3 --n 64 --coarse 32 --train 2000 --test 200 --split
+prints one JSON line with the held-out comparison (training targets solved on the --n grid and
+restricted to the --coarse grid the network predicts).
 """
 import argparse
 import json
@@ -21,17 +22,26 @@ def features(betas, gammas):
     return np.array([[math.log(b)] + list(g) for b, g in zip(betas, gammas)], dtype=np.float32)
 
 
-def solve_targets(instances, n_coarse, L, kernel, dim, batch=100, tau=0.5, eps0=1e-9, progress=False):
-    """Ground states of the instances on the coarse grid (FP64 flow), batched."""
+def solve_targets(instances, n_solve, n_coarse, L, kernel, dim, batch=100, tau=0.5, eps0=1e-9, split=False,
+                  progress=False):
+    """Ground states of the instances solved on the n_solve grid (FP64 flow, batched; split: the 3D
+    potential by Eq. '3.9'), restricted to the coarse grid the network predicts: every
+    (n_solve / n_coarse)-th point, both grids holding x_j = -L + j h on the same box."""
     import torch
+    if n_solve % n_coarse:
+        raise ValueError("the solve grid must refine the coarse grid")
+    step = n_solve // n_coarse
     out = []
     for s in range(0, len(instances), batch):
         if progress:
             print(f"targets {s}/{len(instances)}", file=sys.stderr, flush=True)
         part = instances[s:s + batch]
-        plan = nlf.Plan((n_coarse,) * dim, (L,) * dim, kernel, batch=len(part))
+        plan = nlf.Plan((n_solve,) * dim, (L,) * dim, kernel, batch=len(part), split=split)
         psi, st, status = plan.ground_state([d["beta"] for d in part], [d["gamma"] for d in part],
                                             tau=tau, eps0=eps0, max_iter=20000)
+        if status != nlf.OK:
+            raise RuntimeError(f"target solves returned status {status}")
+        psi = psi.reshape((len(part),) + (n_solve,) * dim)[(slice(None),) + (slice(None, None, step),) * dim]
         out.append(psi.reshape(len(part), -1).float())
         del plan
     return torch.cat(out)
@@ -93,6 +103,8 @@ def main():
     ap.add_argument("--dim", type=int, default=3)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--coarse", type=int, default=32)
+    ap.add_argument("--target-n", type=int, default=0,
+                    help="grid the training targets are solved on (default: --n), restricted to --coarse")
     ap.add_argument("--L", type=float, default=8.0)
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--test", type=int, default=200)
@@ -108,7 +120,9 @@ def main():
     tr = mk(0, args.train)
     te = mk(1, args.test)
     t0 = time.perf_counter()
-    T = solve_targets(tr, args.coarse, args.L, kernel, args.dim, progress=True)
+    tn = args.target_n or args.n
+    split = bool(args.split and args.dim == 3)
+    T = solve_targets(tr, tn, args.coarse, args.L, kernel, args.dim, split=split, progress=True)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     print(f"targets: {len(tr)} solves in {t_data:.1f} s", file=sys.stderr, flush=True)
@@ -119,12 +133,12 @@ def main():
     t_train = time.perf_counter() - t0
     print(f"trained: loss {hist[0]:.3e} -> {hist[-1]:.3e} in {t_train:.1f} s", file=sys.stderr, flush=True)
     # held-out prediction error on the coarse grid
-    Tt = solve_targets(te, args.coarse, args.L, kernel, args.dim)
+    Tt = solve_targets(te, tn, args.coarse, args.L, kernel, args.dim, split=split)
     Xt = torch.tensor(features([d["beta"] for d in te], [d["gamma"] for d in te]), device="cuda")
     Yt = model.forward(Xt)
     rel = ((Yt - Tt).abs().amax(1) / Tt.abs().amax(1)).cpu().numpy()
-    res = {"dim": args.dim, "n": args.n, "coarse": args.coarse, "train": args.train, "test": args.test,
-           "split": bool(args.split and args.dim == 3),
+    res = {"dim": args.dim, "n": args.n, "coarse": args.coarse, "target_n": tn, "train": args.train, "test": args.test,
+           "split": split,
            "hidden": args.hidden, "epochs": args.epochs, "seconds_data": t_data, "seconds_train": t_train,
            "final_train_loss": float(hist[-1]), "heldout_coarse_rel_err_median": float(np.median(rel)),
            "heldout_coarse_rel_err_max": float(rel.max())}

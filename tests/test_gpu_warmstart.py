@@ -75,11 +75,13 @@ def test_resampling_is_band_limited_interpolation(dim):
 
 
 def test_learned_start_saves_iterations_2d():
-    """Small end-to-end run: targets from the library's own solver on a 16^2 grid of [-8,8]^2,
-    96 training instances, 12 held out solved on 64^2 to eps0 = 1e-10 from both starts."""
+    """Small end-to-end run: targets from the library's own solver on the 64^2 grid of [-8,8]^2
+    restricted to the 16^2 grid the network predicts, 96 training instances, 12 held out solved on
+    64^2 to eps0 = 1e-10 from both starts."""
     tr = inputs.warmstart_instances_2d(0, 96)
     te = inputs.warmstart_instances_2d(1, 12)
-    T = warmstart.solve_targets(tr, 16, 8.0, nlf.COULOMB2D, 2, batch=96)
+    T = warmstart.solve_targets(tr, 64, 16, 8.0, nlf.COULOMB2D, 2, batch=96)
+    assert T.shape == (96, 16 * 16)
     X = torch.tensor(warmstart.features([d["beta"] for d in tr], [d["gamma"] for d in tr]), device="cuda")
     model, hist = warmstart.train_model(X, T, hidden=64, epochs=1500, lr=3e-3)
     assert hist[-1] < 1e-2 * hist[0]

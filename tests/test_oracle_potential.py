@@ -225,3 +225,18 @@ def test_confined2d_small_eps_is_coulomb2d():
     assert np.max(np.abs(u0 - uc)) < 1e-14 * np.max(np.abs(uc))
     d = np.max(np.abs(u3 - uc)) / np.max(np.abs(uc))
     assert 1e-5 < d < 1e-2
+
+
+def test_anisotropic_closed_forms_reduce_to_isotropic():
+    """The anisotropic closed forms at equal widths are the isotropic ones: Example 2.1's gamma != 1
+    integral at gamma = 1 (erf formula) and the heat-semigroup 2D Laplace formula at a = b (the
+    E1 formula of Example 2.3), at points along a skew direction."""
+    for r in (0.0, 0.3, 1.0, 2.5, 4.0):
+        x, y, z = 0.48 * r, 0.6 * r, 0.64 * r
+        want = float(cf.coulomb3d_gauss(np.array(r), 1.3))
+        got = float(cf.coulomb3d_gauss_aniso(x, y, z, 1.3, 1.0))
+        assert abs(got - want) <= 1e-12 * abs(want)
+        x2, y2 = 0.6 * r, 0.8 * r
+        want2 = float(cf.laplace2d_gauss(np.array(r), 0.8))
+        got2 = float(cf.laplace2d_gauss_aniso(x2, y2, 0.8, 0.8))
+        assert abs(got2 - want2) <= 1e-11 * max(1.0, abs(want2))
