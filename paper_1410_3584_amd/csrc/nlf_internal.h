@@ -139,7 +139,7 @@ struct nlf_plan {
     int ntred = 0;
     double* iacc = nullptr;     // [batch][Mh] complex FP64: tile-gathered interpolation sums
     void* wtab = nullptr;       // 2D gather plans: [Mh][8] (g, r) tile start weights (nufft.hip)
-    void* itab = nullptr;       // 2D FP64 plans: [Mh][4][2] (g, r) interpolation start weights
+    void* itab = nullptr;       // 2D plans: [Mh][4][2] (g, r) interpolation start weights
     // spreading work decomposition (nlf_plan_set_spread / nlf_plan_autotune)
     int spread_mode = 0;        // NLF_SPREAD_GATHER or NLF_SPREAD_SCATTER
     int spread_kc = 64;         // candidates per block of the gather kernel
@@ -206,7 +206,7 @@ int fold_c(nlf_plan* p, const void* c);                       // canonical full 
 int potential(nlf_plan* p, const void* rho, void* u);
 bool weight_table_fits(const nlf_plan* p);                    // 2D plans whose spreading can use a weight table
 int build_weight_table(nlf_plan* p);                          // allocate and fill p->wtab (needs p->s)
-int build_interp_table(nlf_plan* p);                          // 2D FP64: allocate and fill p->itab (needs p->s, chunks)
+int build_interp_table(nlf_plan* p);                          // 2D: allocate and fill p->itab (needs p->s, chunks)
 
 // harmonic-oscillator Gaussian initial guesses of the plan's fields (unnormalised), solvers.hip
 int ho_guess(nlf_plan* p, const nlf_phys* phys, void* out);

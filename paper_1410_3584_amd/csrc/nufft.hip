@@ -66,9 +66,9 @@ __global__ void k_weight_table(const double* __restrict__ s0, const double* __re
     }
 }
 
-// The interpolation table of a 2D FP64 plan (see NodeArgs::itab), one workgroup per chunk: node t
-// of a chunk belongs to the group of 16 starting at t - t mod 16 (k_binterp2's wave groups).
-template <int MSP>
+// The interpolation table of a 2D plan (see NodeArgs::itab), one workgroup per chunk: node t of a
+// chunk belongs to the group of 16 starting at t - t mod 16 (the interpolation's wave groups).
+template <int MSP, bool F32>
 __global__ void k_interp_table(const Chunk* __restrict__ chunks, const double* __restrict__ s0,
                                const double* __restrict__ s1, int Mr0, int Mr1, double alpha, double2* __restrict__ it) {
     const Chunk ch = chunks[blockIdx.x];
@@ -80,32 +80,45 @@ __global__ void k_interp_table(const Chunk* __restrict__ chunks, const double* _
     const int c0 = wrap((int)floor(s1[first]), Mr1) - ch.t1 * 16;
     for (int ka = 0; ka < 4; ++ka) {
         double2 wy, wx;
-        binterp2_starts<MSP>(s0[node] - f0, s1[node] - f1, rx0, ry0, c0, ka, alpha, wy, wx);
+        if (F32) binterp2_32_starts<MSP>(s0[node] - f0, s1[node] - f1, rx0, ry0, c0, ka, alpha, wy, wx);
+        else binterp2_starts<MSP>(s0[node] - f0, s1[node] - f1, rx0, ry0, c0, ka, alpha, wy, wx);
         it[2 * (4 * (long long)node + ka)] = wy;
         it[2 * (4 * (long long)node + ka) + 1] = wx;
     }
 }
 
-template <int MSP>
+template <int MSP, bool F32>
 static int interp_table_t(nlf_plan* p) {
     NLF_TRY(dev_alloc(p, &p->itab, (size_t)p->Mh * 8 * sizeof(double2)));
-    hipLaunchKernelGGL((k_interp_table<MSP>), dim3(p->nchunks), dim3(kChunk), 0, p->stream, p->chunks, p->s[0], p->s[1],
-                       p->Mr[0], p->Mr[1], p->gc.alpha, reinterpret_cast<double2*>(p->itab));
+    hipLaunchKernelGGL((k_interp_table<MSP, F32>), dim3(p->nchunks), dim3(kChunk), 0, p->stream, p->chunks, p->s[0],
+                       p->s[1], p->Mr[0], p->Mr[1], p->gc.alpha, reinterpret_cast<double2*>(p->itab));
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
 
 int build_interp_table(nlf_plan* p) {
-    if (p->dim != 2 || p->prec != NLF_F64 || p->nchunks == 0) return NLF_OK;
+    if (p->dim != 2 || p->nchunks == 0) return NLF_OK;
+    if (p->prec == NLF_F64) {
+        switch (p->msp) {
+            case 8: return interp_table_t<8, false>(p);
+            case 9: return interp_table_t<9, false>(p);
+            case 10: return interp_table_t<10, false>(p);
+            case 11: return interp_table_t<11, false>(p);
+            case 12: return interp_table_t<12, false>(p);
+            case 13: return interp_table_t<13, false>(p);
+            case 14: return interp_table_t<14, false>(p);
+            case 16: return interp_table_t<16, false>(p);
+            default: return NLF_OK;
+        }
+    }
     switch (p->msp) {
-        case 8: return interp_table_t<8>(p);
-        case 9: return interp_table_t<9>(p);
-        case 10: return interp_table_t<10>(p);
-        case 11: return interp_table_t<11>(p);
-        case 12: return interp_table_t<12>(p);
-        case 13: return interp_table_t<13>(p);
-        case 14: return interp_table_t<14>(p);
-        case 16: return interp_table_t<16>(p);
+        case 4: return interp_table_t<4, true>(p);
+        case 5: return interp_table_t<5, true>(p);
+        case 6: return interp_table_t<6, true>(p);
+        case 7: return interp_table_t<7, true>(p);
+        case 8: return interp_table_t<8, true>(p);
+        case 9: return interp_table_t<9, true>(p);
+        case 10: return interp_table_t<10, true>(p);
         default: return NLF_OK;
     }
 }
@@ -151,9 +164,14 @@ static int interp_t(nlf_plan* p, const EpiArgs& ea, bool zero_b) {
             return record(rec, d ? TK_BINTERP_D : TK_BINTERP_F, grid, 0, t);
         }
         if constexpr (std::is_same<T, float>::value) {   // FP32 plans: the FP32 matrix cores
-            hipLaunchKernelGGL((k_binterp2_32<MSP>), grid, dim3(256), 0, p->stream,
-                               reinterpret_cast<const float2*>(p->grid_a), p->G, na, ea, qq4, exp(-2.0 * p->gc.alpha),
-                               zb, (long long)(bbytes / 16));
+            if (p->itab)
+                hipLaunchKernelGGL((k_binterp2_32<MSP, true>), grid, dim3(256), 0, p->stream,
+                                   reinterpret_cast<const float2*>(p->grid_a), p->G, na, ea, qq4,
+                                   exp(-2.0 * p->gc.alpha), zb, (long long)(bbytes / 16));
+            else
+                hipLaunchKernelGGL((k_binterp2_32<MSP, false>), grid, dim3(256), 0, p->stream,
+                                   reinterpret_cast<const float2*>(p->grid_a), p->G, na, ea, qq4,
+                                   exp(-2.0 * p->gc.alpha), zb, (long long)(bbytes / 16));
         } else if (p->itab) {
             hipLaunchKernelGGL((k_binterp2<T, MSP, true>), grid, dim3(256), 0, p->stream,
                                reinterpret_cast<const V2<T>*>(p->grid_a), p->G, na, ea, qq4, zb,

@@ -72,9 +72,10 @@ struct NodeArgs {
     // and t1 along axis 1, for the (at most 4 consecutive) tiles its stencil overlaps: the tiles
     // whose explicit candidate lists hold the node
     const double2* wtab;
-    // 2D FP64 plans (nlf_plan::itab): per sorted node m and lane quarter ka = 0..3 of the per-bin
+    // 2D plans (nlf_plan::itab): per sorted node m and lane quarter ka = 0..3 of the per-bin
     // interpolation, itab[2 (4 m + ka)] = (g, r) of its y-weights and itab[2 (4 m + ka) + 1] of
-    // its x-weights: the start values of the step-4 recurrences of k_binterp2
+    // its x-weights: the start values of the weight recurrences of k_binterp2 (FP64 plans,
+    // binterp2_starts) or k_binterp2_32 (FP32 plans, binterp2_32_starts)
     const double2* itab;
 };
 
@@ -942,6 +943,17 @@ __device__ __forceinline__ void binterp2_starts(double d0, double d1, int rx0, i
     wx = make_double2(exp(-alpha * x0 * x0), exp(-alpha * (8.0 * x0 + 16.0)));
 }
 
+// The same for k_binterp2_32, whose lane quarter ka takes the x-weights of rows 4 (ka mod 2) + v
+// (+ 8 rb) by a unit-step recurrence: r = exp(-alpha (2 x + 1)) at the first of them.
+template <int MSP>
+__device__ __forceinline__ void binterp2_32_starts(double d0, double d1, int rx0, int ry0, int c0, int ka, double alpha,
+                                                   double2& wy, double2& wx) {
+    const double y0 = (double)(c0 + ka - ry0 - (MSP - 1)) - d1;
+    wy = make_double2(exp(-alpha * y0 * y0), exp(-alpha * (8.0 * y0 + 16.0)));
+    const double x0 = (double)(4 * (ka & 1) - rx0 - (MSP - 1)) - d0;
+    wx = make_double2(exp(-alpha * x0 * x0), exp(-alpha * (2.0 * x0 + 1.0)));
+}
+
 template <typename T, int MSP, bool ITAB = false>
 __device__ __forceinline__ void binterp2_body(const V2<T>* __restrict__ grid, long long gstride, const NodeArgs& na,
                                               const EpiArgs& ea, double qq4, double2* __restrict__ zero,
@@ -1109,7 +1121,7 @@ struct Binterp2Lds32 {
                                  2 * PL * (int)sizeof(float);
 };
 
-template <int MSP>
+template <int MSP, bool ITAB = false>
 __device__ __forceinline__ void binterp2_32_body(const float2* __restrict__ grid, long long gstride, const NodeArgs& na,
                                                  const EpiArgs& ea, double qq4, double qq1, double2* __restrict__ zero,
                                                  long long zero16, VBlk vb, unsigned char* smem) {
@@ -1173,12 +1185,18 @@ __device__ __forceinline__ void binterp2_32_body(const float2* __restrict__ grid
         float bv[KS];
         double wx[RBX][4];
         if (jn < ch.count) {
-            const double d0 = nd[jn][0], d1 = nd[jn][1];
             const int rx0 = noff[jn][0], ry0 = noff[jn][1];
+            double2 sy, sx;   // start values of the y- and x-weight recurrences
+            if (ITAB) {   // the plan's table of these start values (fixed node positions)
+                const double2* it2 = na.itab + 2 * (4 * (long long)(ch.start + jn) + ka);
+                sy = it2[0];
+                sx = it2[1];
+            } else {
+                binterp2_32_starts<MSP>(nd[jn][0], nd[jn][1], rx0, ry0, c0, ka, alpha, sy, sx);
+            }
             {   // y-weights of columns c0 + 4 st + ka
                 const int q0 = c0 + ka - ry0;
-                const double x0 = (double)(q0 - (MSP - 1)) - d1;
-                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (8.0 * x0 + 16.0));
+                double gg = sy.x, rr = sy.y;
 #pragma unroll
                 for (int st = 0; st < KS; ++st) {
                     const int q = q0 + 4 * st;
@@ -1189,8 +1207,7 @@ __device__ __forceinline__ void binterp2_32_body(const float2* __restrict__ grid
             }
             {   // x-weights of rows X = xb + 8 rb + v by the unit-step recurrence over X = xb .. 8 RBX - 1
                 const int q0 = xb - rx0;
-                const double x0 = (double)(q0 - (MSP - 1)) - d0;
-                double gg = exp(-alpha * x0 * x0), rr = exp(-alpha * (2.0 * x0 + 1.0));
+                double gg = sx.x, rr = sx.y;
 #pragma unroll
                 for (int rb = 0; rb < RBX; ++rb) {
 #pragma unroll
@@ -1236,12 +1253,12 @@ __device__ __forceinline__ void binterp2_32_body(const float2* __restrict__ grid
     }
 }
 
-template <int MSP>
+template <int MSP, bool ITAB>
 __global__ void __launch_bounds__(256, 3) k_binterp2_32(const float2* __restrict__ grid, long long gstride,
                                                         NodeArgs na, EpiArgs ea, double qq4, double qq1,
                                                         double2* __restrict__ zero, long long zero16) {
     __shared__ __align__(16) unsigned char smem[Binterp2Lds32<MSP>::bytes];
-    binterp2_32_body<MSP>(grid, gstride, na, ea, qq4, qq1, zero, zero16, hw_block(), smem);
+    binterp2_32_body<MSP, ITAB>(grid, gstride, na, ea, qq4, qq1, zero, zero16, hw_block(), smem);
 }
 
 // ---- tile-gathered interpolation on the FP64 matrix cores -----------------------------------------

@@ -749,7 +749,7 @@ static int build(nlf_plan* p, const nlf_box* box, int kernel, const nlf_opts* o)
     if (kernel == NLF_LAPLACE2D) NLF_TRY(upload(p, (void**)&p->gk, gk.data(), Mh * sizeof(double)));
     NLF_TRY(upload(p, (void**)&p->perm, order.data(), Mh * sizeof(int)));
     NLF_TRY(upload(p, (void**)&p->chunks, chunks.data(), chunks.size() * sizeof(Chunk)));
-    NLF_TRY(build_interp_table(p));   // 2D FP64: the interpolation's per-node start weights (128 bytes per node)
+    NLF_TRY(build_interp_table(p));   // 2D: the interpolation's per-node start weights (128 bytes per node)
     for (int i = 0; i < p->dim; ++i) {
         // 1 / c_g(j') with c_g(j') = sqrt(tau/pi) exp(-tau j'^2): the Fourier coefficients of the
         // periodised Gaussian exp(-x^2/(4 tau)), tau = pi msp / (3 n^2)
