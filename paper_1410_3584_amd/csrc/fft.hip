@@ -171,6 +171,128 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
     return launch_cols_cfg<T, DIR, LP, SP, FftCfg<T>::NT, FftCfg<T>::E, false>(p, a, outer, batch);
 }
 
+// The fused axis-0 pass of a split's I1 with the lines in registers, for columns of n = 8^P points
+// (512 at 256^3).  Thread t of a column holds the 8 elements t + m n/8 (m = 0..7) of its line, which
+// are exactly the inputs of a radix-8 Stockham butterfly of the first pass; between passes the
+// outputs go through LDS once (written at their Stockham positions, read back as the next pass's
+// inputs).  After the last forward pass thread t holds the frequencies t + m n/8, which are again
+// the inverse transform's first inputs: the multiply by w and both transforms share registers, and
+// LDS carries only the 2 (P - 1) exchanges, instead of a read and a write per pass plus the staging
+// of the load, the multiply and the store.  C columns per workgroup, 64 n / 512 threads each.
+constexpr int kConv0rC = 8;   // columns per workgroup of k_fft_conv0r (128-byte row segments)
+
+template <typename T, int P, int C>
+__global__ void __launch_bounds__(C * (1 << (3 * P - 3))) k_fft_conv0r(ColsArgs a, ConvW cw) {
+    constexpr int LG = 3 * P, N = 1 << LG, Q = N / 8;   // line length, threads (butterflies) per line
+    constexpr int PITCH = N + (N >> 3) + 1;             // padded line (one slot per 8) + 1
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    V2<T>* tw = buf + C * PITCH;                        // half twiddle table, w^t for t < N/2
+    const int tid = threadIdx.x;
+    const int c = tid % C, t = tid / C;                 // C adjacent columns per row segment
+    int cb = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) cb = (cb & 7) * (nb >> 3) + (cb >> 3);   // XCD-contiguous column blocks
+    const long long col = (long long)cb * C + c;
+    V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride + col;
+    V2<T> x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {   // the data rows of the padded column; the rest are zero
+        const int r = t + m * Q;
+        x[m] = is_data_row(r, a.nd, N) ? base[(long long)r * a.inner] : mk<T>(0, 0);
+    }
+    for (int i = tid; i < N / 2; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    V2<T>* line = buf + c * PITCH;
+    // one radix-8 pass on the registers: butterfly t, p = 8^s, inputs x[m] = line[t + m Q]
+    auto pass = [&](int s, auto dir) {
+        constexpr int DIR = decltype(dir)::value;
+        const int p = 1 << (3 * s), k = t & (p - 1);
+        if (s > 0) {
+            const int lts = LG - 3 - 3 * s;   // twiddle stride n / (8 p)
+#pragma unroll
+            for (int m = 1; m < 8; ++m) {
+                const int tt = (m * k) << lts;
+                V2<T> w = tw[tt < N / 2 ? tt : tt - N / 2];
+                if (tt >= N / 2) { w.x = -w.x; w.y = -w.y; }
+                if (DIR > 0) w.y = -w.y;
+                x[m] = cmul<T>(x[m], w);
+            }
+        }
+        dft8<T, DIR>(x);
+    };
+    // outputs of pass s to their Stockham positions, then the next pass's inputs
+    auto exchange = [&](int s) {
+        const int p = 1 << (3 * s), k = t & (p - 1);
+        const int j = (t - k) * 8 + k;
+        __syncthreads();   // the previous exchange's reads are done
+#pragma unroll
+        for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+    };
+    __syncthreads();   // twiddles staged
+    using Fwd = std::integral_constant<int, -1>;
+    using Inv = std::integral_constant<int, 1>;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        pass(s, Fwd{});
+        if (s + 1 < P) exchange(s);
+    }
+    // thread t holds frequencies t + m Q: multiply by w(k) (column terms once per thread, as in
+    // k_fft_conv0; expm1 where 1 - e^{-x} would cancel)
+    {
+        const int c1 = (int)(col / cw.pitch2), c2 = (int)(col - (long long)c1 * cw.pitch2);
+        const double k1 = (c1 < cw.Mr1 / 2 ? c1 : c1 - cw.Mr1) * cw.dk1;
+        const double k2 = (c2 < cw.Mr2 / 2 ? c2 : c2 - cw.Mr2) * cw.dk2;
+        const double q12 = k1 * k1 + k2 * k2;
+        const double e12 = exp(-q12 * cw.inva);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int r = t + m * Q;
+            const double k0 = (r < cw.Mr0 / 2 ? r : r - cw.Mr0) * cw.dk0;
+            const double kk = k0 * k0 + q12;
+            const double xx = kk * cw.inva;
+            double w;
+            if (xx >= 1.0) w = (1.0 - exp(-k0 * k0 * cw.inva) * e12) / kk;
+            else w = kk > 0.0 ? -expm1(-xx) / kk : cw.inva;
+            x[m].x = (T)((double)x[m].x * w);
+            x[m].y = (T)((double)x[m].y * w);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        pass(s, Inv{});
+        if (s + 1 < P) exchange(s);
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {   // outputs t + m Q: the data rows only
+        const int r = t + m * Q;
+        if (is_data_row(r, a.nd, N)) base[(long long)r * a.inner] = x[m];
+    }
+}
+
+template <typename T, int P, int C>
+static int launch_conv0r(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
+    constexpr int N = 1 << (3 * P), NT = C * N / 8;
+    a.ncb = (int)(a.inner / C);
+    dim3 grid(a.ncb, 1, batch);
+    const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);
+    static std::mutex attr_mu;
+    static bool raised = false;
+    {
+        std::lock_guard<std::mutex> lock(attr_mu);
+        if (!raised) {
+            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_conv0r<T, P, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+            raised = true;
+        }
+    }
+    hipLaunchKernelGGL((k_fft_conv0r<T, P, C>), grid, dim3(NT), lds, p->stream, a, cw);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
 template <typename T, int NT, int E, bool TWL>
 static int launch_conv0_cfg(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     a.lg = ilog2(a.n);
@@ -235,7 +357,9 @@ static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
     cw.dk0 = 2.0 * 3.14159265358979323846 / (p->Mr[0] * p->h[0]);
     cw.dk1 = 2.0 * 3.14159265358979323846 / (p->Mr[1] * p->h[1]);
     cw.dk2 = 2.0 * 3.14159265358979323846 / (p->Mr[2] * p->h[2]);
-    if (c0.n <= 512) NLF_TRY((launch_conv0_cfg<T, ColSmallCfg::NT, ColSmallCfg::E, true>(p, c0, cw, p->batch)));
+    if (c0.n == 512 && c0.inner % kConv0rC == 0)   // lines in registers
+        NLF_TRY((launch_conv0r<T, 3, kConv0rC>(p, c0, cw, p->batch)));
+    else if (c0.n <= 512) NLF_TRY((launch_conv0_cfg<T, ColSmallCfg::NT, ColSmallCfg::E, true>(p, c0, cw, p->batch)));
     else NLF_TRY((launch_conv0_cfg<T, FftCfg<T>::NT, FftCfg<T>::E, false>(p, c0, cw, p->batch)));
     c.nd = p->n[1];
     NLF_TRY((launch_cols<T, 1, false, true>(p, c, p->n[0], p->batch)));
