@@ -160,10 +160,127 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     return NLF_OK;
 }
 
+// Strided-axis pass of n = 2^LG-point lines with the lines in registers, for n = 512 = 8 x 8 x 8
+// and n = 1024 = 2 x 8 x 8 x 8 (the oversampled axes of the 256^3 and 512^2 grids).  Thread t of a
+// column holds the 8 elements t + m n/8 (m = 0..7).  With a radix-2 factor, its registers m and
+// m + 4 are the two inputs of the first pass's butterflies t + m n/8 (m < 4); then radix-8
+// passes, one butterfly per thread, with an exchange through LDS before each (outputs written at
+// their Stockham positions, the next inputs read back).  After the last pass thread t holds the
+// outputs t + m n/8, stored directly: LG/3 exchanges (3 at 1024, 2 at 512) instead of a read and a
+// write per pass plus the staging of the load and the store.  The passes are those of lds_fft
+// (radix 2 first, then radix 8); the twiddles come from the half table, w^(t + n/2) = -w^t.  C
+// columns per workgroup, C n / 8 threads.
+template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int LG, int C>
+__global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) {
+    static_assert(LG % 3 == 0 || LG % 3 == 1, "radix 8 passes after at most one radix-2 pass");
+    constexpr int N = 1 << LG, Q = N / 8, R2 = LG % 3;   // R2: a first radix-2 pass
+    constexpr int PITCH = N + (N >> 3) + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    V2<T>* tw = buf + C * PITCH;   // half twiddle table, w^t for t < N/2
+    const int tid = threadIdx.x;
+    const int c = tid % C, t = tid / C;
+    if (a.mom && blockIdx.x == 0 && blockIdx.y == 0) finish_moments(a, blockIdx.z, C * Q);
+    int cb = blockIdx.x;
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) cb = (cb & 7) * (nb >> 3) + (cb >> 3);   // XCD-contiguous column blocks
+    const int o = blockIdx.y;
+    const long long go = a.outer_mapped ? dmap(o, a.outer_nd, a.outer_Mr) : o;
+    V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride + go * (long long)N * a.inner +
+                  (long long)cb * C + c;
+    V2<T> x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int r = t + m * Q;
+        x[m] = (!LPRUNE || is_data_row(r, a.nd, N)) ? base[(long long)r * a.inner] : mk<T>(0, 0);
+    }
+    for (int i = tid; i < N / 2; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    V2<T>* line = buf + c * PITCH;
+    __syncthreads();   // twiddles staged
+    if constexpr (R2) {
+        // pass 0, radix 2 (p = 1): butterfly i = t + Q m (m < 4) takes x[i], x[i + n/2] and writes
+        // positions 2 i and 2 i + 1
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const V2<T> u = x[m], v = x[m + 4];
+            const int i = t + m * Q;
+            line[lpad<true>(2 * i)] = cadd<T>(u, v);
+            line[lpad<true>(2 * i + 1)] = csub<T>(u, v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+    }
+    // radix-8 passes, p = 2^R2 8^s: butterfly t reads x[t + Q m] and writes (t - k) 8 + k + m p
+    constexpr int NP = LG / 3;
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+        const int lgp = R2 + 3 * s, p = 1 << lgp, k = t & (p - 1);
+        if (p > 1) {
+            const int lts = LG - 3 - lgp;   // twiddle stride n / (8 p)
+#pragma unroll
+            for (int m = 1; m < 8; ++m) {
+                const int tt = (m * k) << lts;
+                V2<T> w = tw[tt < N / 2 ? tt : tt - N / 2];
+                if (tt >= N / 2) { w.x = -w.x; w.y = -w.y; }
+                if (DIR > 0) w.y = -w.y;
+                x[m] = cmul<T>(x[m], w);
+            }
+        }
+        dft8<T, DIR>(x);
+        if (s + 1 < NP) {
+            const int j = (t - k) * 8 + k;
+            __syncthreads();   // the previous reads are done
+#pragma unroll
+            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+        }
+    }
+    const int nds = a.nd_store > 0 ? a.nd_store : a.nd;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {   // outputs t + Q m
+        const int r = t + m * Q;
+        if (!SPRUNE || is_data_row(r, nds, N)) base[(long long)r * a.inner] = x[m];
+    }
+}
+
+// 512 threads per workgroup: 4 columns of 1024 points (64-byte row segments) or 8 of 512 (128 bytes)
+template <int LG> constexpr int cols_r_c() { return LG == 10 ? 4 : 8; }
+
+template <typename T, int DIR, bool LP, bool SP, int LG>
+static int launch_cols_r(nlf_plan* p, ColsArgs a, int outer, int batch) {
+    constexpr int C = cols_r_c<LG>(), N = 1 << LG;
+    a.lg = LG;
+    a.C = C;
+    a.ncb = (int)(a.inner / C);
+    dim3 grid(a.ncb, outer, batch);
+    const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);
+    static std::mutex attr_mu;
+    static bool raised = false;
+    {
+        std::lock_guard<std::mutex> lock(attr_mu);
+        if (!raised) {
+            NLF_HIP(hipFuncSetAttribute((const void*)&k_fft_cols_r<T, DIR, LP, SP, LG, C>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            raised = true;
+        }
+    }
+    hipLaunchKernelGGL((k_fft_cols_r<T, DIR, LP, SP, LG, C>), grid, dim3(C * N / 8), lds, p->stream, a);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
 template <typename T, int DIR, bool LP, bool SP>
 static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_cols_cfg<T, DIR, LP, SP, ExecColCfg::NT, ExecColCfg::E, true>(p, a, outer, batch);
+    // lines in registers (not for the band columns of a split's ball; never recorded)
+    if (!recorder() && !a.bc2) {
+        if (a.n == 512 && a.inner % cols_r_c<9>() == 0) return launch_cols_r<T, DIR, LP, SP, 9>(p, a, outer, batch);
+        if (a.n == 1024 && a.inner % cols_r_c<10>() == 0) return launch_cols_r<T, DIR, LP, SP, 10>(p, a, outer, batch);
+    }
     if (a.n <= 512)
         return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E, true>(p, a, outer, batch);
     if (a.n == 1024)

@@ -470,26 +470,30 @@ __device__ __forceinline__ long long band_col(const ColsArgs& a, int cb) {
     return (long long)c1 * a.Mr2 + c2;
 }
 
+// 2D Laplace: one workgroup of the forward column pass adds the row pass's per-workgroup partial
+// sums of rho, x rho, y rho of field z into its moments m0, m1 (uniform over the workgroup)
+__device__ __forceinline__ void finish_moments(const ColsArgs& a, int z, int nt) {
+    __shared__ double red16[16];
+    const double* part = a.mom_part + (long long)z * a.mom_nblk * 3;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < a.mom_nblk; i += nt)
+        for (int k = 0; k < 3; ++k) s[k] += part[3 * i + k];
+    for (int k = 0; k < 3; ++k) s[k] = wg_sum(s[k], red16);
+    if (threadIdx.x == 0) {
+        double* m = a.mom + 4 * z;
+        m[0] = a.mom_w * s[0];
+        m[1] = a.mom_w * s[1];
+        m[2] = a.mom_w * s[2];
+        m[3] = 0.0;
+    }
+}
+
 template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int NT, int E, bool TWL>
 __device__ __forceinline__ void fft_cols_body(const ColsArgs& a, VBlk vb, unsigned char* smem_raw) {
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
     const int n = a.n, C = a.C, lgC = __builtin_ctz(C);   // C is a power of two
     const int pitch = lds_line(n, TWL) + 1;
-    if (a.mom && vb.x == 0 && vb.y == 0) {   // uniform over the workgroup
-        __shared__ double red16[16];
-        const double* part = a.mom_part + (long long)vb.z * a.mom_nblk * 3;
-        double s[3] = {0.0, 0.0, 0.0};
-        for (int i = threadIdx.x; i < a.mom_nblk; i += NT)
-            for (int k = 0; k < 3; ++k) s[k] += part[3 * i + k];
-        for (int k = 0; k < 3; ++k) s[k] = wg_sum(s[k], red16);
-        if (threadIdx.x == 0) {
-            double* m = a.mom + 4 * vb.z;
-            m[0] = a.mom_w * s[0];
-            m[1] = a.mom_w * s[1];
-            m[2] = a.mom_w * s[2];
-            m[3] = 0.0;
-        }
-    }
+    if (a.mom && vb.x == 0 && vb.y == 0) finish_moments(a, vb.z, NT);   // uniform over the workgroup
     // XCD-aware order: consecutive hardware workgroup ids go round-robin over the 8 XCDs; give
     // each XCD a contiguous range of column blocks so neighbouring row segments share its L2.
     int cb = vb.x;
