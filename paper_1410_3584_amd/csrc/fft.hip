@@ -103,15 +103,189 @@ static int launch_rows_cfg(nlf_plan* p, RowsArgs a, int batch) {
     return NLF_OK;
 }
 
+// Contiguous-axis pass of 1024-point lines of a 2D grid with the lines in registers (the passes of
+// k_fft_cols_r): L lines per workgroup, 128 threads per line, thread t holding the elements
+// t + 128 m of its line, so that a wave's loads and stores are contiguous.  The fused prologue and
+// epilogue are those of fft_rows_body for 2D lines: LOAD_RHO reads the density's data row into the
+// oversampled positions with the precorrection (and the Laplace moments' partial sums, and the
+// non-finite check), STORE_U writes the data positions of the real part with the postcorrection
+// (and the analytic u1 of the Laplace kernel); LOAD_GRID / STORE_GRID move whole lines.
+template <typename T, typename TIO, int DIR, int LOAD, int STORE, int L>
+__global__ void __launch_bounds__(L * 128) k_fft_rows_r(RowsArgs a) {
+    constexpr int LG = 10, N = 1 << LG, Q = N / 8;
+    constexpr int PITCH = N + (N >> 3) + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    V2<T>* tw = buf + L * PITCH;   // half twiddle table
+    const int tid = threadIdx.x;
+    const int l = tid / Q, t = tid % Q;
+    const int b = blockIdx.y;
+    const int al = blockIdx.x * L + l;   // data line (row j0 of the 2D data grid when mapped)
+    const bool valid = al < a.nlines;
+    constexpr bool mapped = (LOAD == LOAD_RHO) || (STORE == STORE_U);
+    const int ndl = a.nd[1];
+    const long long gl = mapped ? dmap(valid ? al : 0, a.nd[0], a.Mr[0]) : al;
+    const double fac = (mapped && valid) ? a.dec0[al] : 1.0;
+    V2<T>* grid = reinterpret_cast<V2<T>*>(a.grid) + (long long)b * a.gstride;
+    V2<T> x[8];
+    if (LOAD == LOAD_RHO) {
+        const TIO* rho = reinterpret_cast<const TIO*>(a.rho) + (long long)b * a.rstride + (long long)al * ndl;
+        double m0 = 0.0, mx = 0.0, my = 0.0;
+        double rv[8], dv[8];   // every load issued before the first use
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            rv[m] = 0.0;
+            dv[m] = 0.0;
+            if (valid && is_data_row(c, ndl, N)) {   // oversampled position c holds data index j
+                const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+                rv[m] = (double)rho[j];
+                dv[m] = a.dec1[j];
+            }
+        }
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+            bad = bad || !isfinite(rv[m]);
+            x[m] = mk<T>((T)(rv[m] * fac * dv[m]), 0);
+            if (a.mom_part && is_data_row(c, ndl, N)) {
+                m0 += rv[m];
+                mx += rv[m] * (-a.L0 + al * a.h0);
+                my += rv[m] * (-a.L1 + j * a.h1);
+            }
+        }
+        if (a.nonfinite && bad) atomicOr(a.nonfinite, 1);
+        if (a.mom_part) {   // uniform over the workgroup
+            __shared__ double red16[16];
+            m0 = wg_sum(m0, red16);
+            mx = wg_sum(mx, red16);
+            my = wg_sum(my, red16);
+            if (tid == 0) {
+                double* o = a.mom_part + ((long long)b * gridDim.x + blockIdx.x) * 3;
+                o[0] = m0;
+                o[1] = mx;
+                o[2] = my;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = valid ? grid[gl * N + t + m * Q] : mk<T>(0, 0);
+    }
+    // STORE_U: the epilogue's per-element factors, loaded before the transform
+    double pv[8], uv[8], m0 = 0, m1x = 0, m1y = 0;
+    if (STORE == STORE_U) {
+        if (a.add_u1) {
+            m0 = a.mom[4 * b + 0];
+            m1x = a.mom[4 * b + 1];
+            m1y = a.mom[4 * b + 2];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+            pv[m] = 0.0;
+            uv[m] = 0.0;
+            if (valid && is_data_row(c, ndl, N)) {
+                pv[m] = a.dec1[j];
+                if (a.add_u1) uv[m] = a.u11[(long long)al * ndl + j];
+            }
+        }
+    }
+    for (int i = tid; i < N / 2; i += L * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    V2<T>* line = buf + l * PITCH;
+    __syncthreads();   // twiddles staged
+    // radix 2 (p = 1) on the registers m, m + 4, then three radix-8 passes (as in k_fft_cols_r)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const V2<T> u = x[m], v = x[m + 4];
+        const int i = t + m * Q;
+        line[lpad<true>(2 * i)] = cadd<T>(u, v);
+        line[lpad<true>(2 * i + 1)] = csub<T>(u, v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int lgp = 1 + 3 * s, p = 1 << lgp, k = t & (p - 1);
+        const int lts = LG - 3 - lgp;
+#pragma unroll
+        for (int m = 1; m < 8; ++m) {
+            const int tt = (m * k) << lts;
+            V2<T> w = tw[tt < N / 2 ? tt : tt - N / 2];
+            if (tt >= N / 2) { w.x = -w.x; w.y = -w.y; }
+            if (DIR > 0) w.y = -w.y;
+            x[m] = cmul<T>(x[m], w);
+        }
+        dft8<T, DIR>(x);
+        if (s < 2) {
+            const int j = (t - k) * 8 + k;
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+        }
+    }
+    if (!valid) return;
+    if (STORE == STORE_GRID) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) grid[gl * N + t + m * Q] = x[m];
+    } else {
+        TIO* u = reinterpret_cast<TIO*>(a.u) + (long long)b * a.rstride + (long long)al * ndl;
+        const double inv2s2 = 1.0 / (2.0 * a.sigma * a.sigma);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            if (!is_data_row(c, ndl, N)) continue;
+            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+            double val = (double)x[m].x * fac * pv[m] * a.post;
+            if (a.add_u1) {   // u_{1,2} as in fft_rows_body (Eq. 'phi12_ext')
+                const double xx = -a.L0 + al * a.h0, yy = -a.L1 + j * a.h1;
+                const double r2 = xx * xx + yy * yy;
+                const double f = (r2 > 0) ? expm1(-r2 * inv2s2) / (2.0 * 3.14159265358979323846 * r2) : 0.0;
+                val += m0 * uv[m] - (m1x * f * xx + m1y * f * yy);
+            }
+            u[j] = a.accum ? (TIO)((double)u[j] + val) : (TIO)val;
+        }
+    }
+}
+
+// lines per workgroup of k_fft_rows_r.  Measured at 512^2 (FP64 evaluation, forward + inverse
+// FFT stages, us): one line per workgroup 20.1-20.5 + 19.9-20.2, two 20.7-20.8 + 19.0-19.2, the
+// LDS-resident rows (k_fft_rows) 22.1 + 19.7-19.8.
+constexpr int kRowsRL = 1;   // the forward pass (LOAD_RHO), which also sums moments per workgroup
+template <int LOAD> constexpr int rows_r_lines() { return LOAD == LOAD_RHO ? kRowsRL : 2; }
+
+template <typename T, int DIR, int LOAD, int STORE, typename TIO>
+static int launch_rows_r(nlf_plan* p, RowsArgs a, int batch) {
+    constexpr int N = 1024, kRowsRL = rows_r_lines<LOAD>();
+    a.lg = 10;
+    a.lines_per_wg = kRowsRL;
+    dim3 grid((a.nlines + kRowsRL - 1) / kRowsRL, batch);
+    const size_t lds = ((size_t)kRowsRL * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);   // <= 45 KiB
+    hipLaunchKernelGGL((k_fft_rows_r<T, TIO, DIR, LOAD, STORE, kRowsRL>), grid, dim3(kRowsRL * 128), lds, p->stream, a);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+// rows of 1024 points of 2D grids (no Hermitian half, no band) take k_fft_rows_r
+static bool rows_r_applies(const RowsArgs& a) { return a.n == 1024 && a.dim == 2 && !a.half && !a.band; }
+
 // LDS element budget of the contiguous-axis kernel for lines of length n: 1024-point lines get
 // one line per workgroup (twice the workgroups of the 2048-element budget)
 static int rows_budget(int n) { return n == 1024 ? Row1024Cfg::E : RowCfg::E; }
-static int rows_lines_per_wg(int n) { return std::max(1, rows_budget(n) / n); }
+// lines per workgroup of the 2D row pass (the Laplace moments' partial sums are per workgroup)
+static int rows_lines_per_wg(int n) { return n == 1024 ? kRowsRL : std::max(1, rows_budget(n) / n); }
 
 template <typename T, int DIR, int LOAD, int STORE, typename TIO = T>
 static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, ExecRowCfg::E, true>(p, a, batch);
+    if (!recorder() && rows_r_applies(a)) return launch_rows_r<T, DIR, LOAD, STORE, TIO>(p, a, batch);
     if (a.n == 1024)
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, Row1024Cfg::E, Row1024Cfg::TWL, Row1024Cfg::NT>(p, a, batch);
     if (a.n <= 512) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, true>(p, a, batch);

@@ -37,8 +37,10 @@ struct ColSmallCfg { static constexpr int E = 4096, NT = 1024; };
 // element budgets that give each thread as many elements as the kernels' own configurations.
 struct ExecRowCfg { static constexpr int E = 1024, NT = 256; };
 struct ExecColCfg { static constexpr int E = 1024, NT = 256; };
-// 1024-point lines (the oversampled axes of the 512^2 grids).  Measured at 512^2 (FP64 evaluation,
-// forward + inverse FFT stages, us): these shapes 26.7 + 23.3; rows of 128 or 1024 threads per
+// 1024-point lines held in LDS (the oversampled axes of the 512^2 grids; the 2D rows and the columns
+// now take the register-resident kernels of fft.hip, these shapes the lines those do not cover).
+// Measured at 512^2 with the LDS kernels on both axes (FP64 evaluation, forward + inverse FFT
+// stages, us): these shapes 26.7 + 23.3; rows of 128 or 1024 threads per
 // line 27.4-32.9 + 25.3-26.6 (a pass has 128 radix-8 butterflies per line, but the 512 line
 // workgroups then hold too few waves per CU to cover the loads); twiddles in LDS 27.4 + 25.0;
 // column blocks of 2 columns (256 threads) or of 4 with 1024 threads 27.3-27.9 + 25.2-27.0.
