@@ -254,6 +254,163 @@ __global__ void __launch_bounds__(L * 128) k_fft_rows_r(RowsArgs a) {
     }
 }
 
+// Contiguous-axis pass of 512-point lines of a 3D grid with the lines in registers: one wave per
+// line (lane t holds the elements t + 64 m), so the exchanges between the three radix-8 passes
+// stay inside the wave and need no workgroup barrier, only the wave's own LDS writes to have
+// completed.  L lines (waves) per workgroup share the staged twiddle table.  The fused modes are
+// those of fft_rows_body for 3D lines: LOAD_RHO (density row with the precorrection), STORE_U (the
+// data positions of the real part with the postcorrection, optionally added to u), the Hermitian
+// half of a transform of real data (STORE_GRID writes the first `half` outputs, LOAD_GRID rebuilds
+// the rest) and the band of a split's ball (only |f| < band read or written).
+__device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <typename T, typename TIO, int DIR, int LOAD, int STORE, int L>
+__global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
+    constexpr int LG = 9, N = 1 << LG, Q = N / 8;
+    constexpr int PITCH = N + (N >> 3) + 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
+    V2<T>* tw = buf + L * PITCH;   // half twiddle table
+    const int tid = threadIdx.x;
+    const int l = tid >> 6, t = tid & 63;
+    const int b = blockIdx.y;
+    const int al = blockIdx.x * L + l;   // data line j0 nd1 + j1 when mapped
+    const bool valid = al < a.nlines;
+    constexpr bool mapped = (LOAD == LOAD_RHO) || (STORE == STORE_U);
+    const int ndl = a.nd[2];
+    long long gl = al;
+    double fac = 1.0;
+    if (mapped) {
+        const int la = valid ? al : 0;
+        const int j0 = la / a.nd[1], j1 = la - j0 * a.nd[1];
+        gl = (long long)dmap(j0, a.nd[0], a.Mr[0]) * a.Mr[1] + dmap(j1, a.nd[1], a.Mr[1]);
+        fac = a.dec0[j0] * a.dec1[j1];
+    }
+    V2<T>* grid = reinterpret_cast<V2<T>*>(a.grid) + (long long)b * a.gstride;
+    V2<T> x[8];
+    if (LOAD == LOAD_RHO) {
+        const TIO* rho = reinterpret_cast<const TIO*>(a.rho) + (long long)b * a.rstride + (long long)al * ndl;
+        double rv[8], dv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            rv[m] = 0.0;
+            dv[m] = 0.0;
+            if (valid && is_data_row(c, ndl, N)) {   // oversampled position c holds data index j
+                const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+                rv[m] = (double)rho[j];
+                dv[m] = a.dec2[j];
+            }
+        }
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            bad = bad || !isfinite(rv[m]);
+            x[m] = mk<T>((T)(rv[m] * fac * dv[m]), 0);
+        }
+        if (a.nonfinite && bad) atomicOr(a.nonfinite, 1);
+    } else if (a.half) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            const bool lo = c <= (N >> 1);
+            x[m] = mk<T>(0, 0);
+            if (valid) {
+                const V2<T> w = grid[gl * a.half + (lo ? c : N - c)];
+                x[m] = lo ? w : mk<T>(w.x, -w.y);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            x[m] = (valid && (!a.band || is_data_row(c, 2 * a.band, N))) ? grid[gl * N + c] : mk<T>(0, 0);
+        }
+    }
+    // STORE_U: the epilogue's per-element factors (and the values added to), loaded before the transform
+    double pv[8], uo[8];
+    if (STORE == STORE_U) {
+        const TIO* u = reinterpret_cast<const TIO*>(a.u) + (long long)b * a.rstride + (long long)al * ndl;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+            pv[m] = 0.0;
+            uo[m] = 0.0;
+            if (valid && is_data_row(c, ndl, N)) {
+                pv[m] = a.dec2[j];
+                if (a.accum) uo[m] = (double)u[j];
+            }
+        }
+    }
+    for (int i = tid; i < N / 2; i += L * 64) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    V2<T>* line = buf + l * PITCH;
+    __syncthreads();   // twiddles staged; from here on each wave works alone
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int lgp = 3 * s, p = 1 << lgp, k = t & (p - 1);
+        if (s > 0) {
+            const int lts = LG - 3 - lgp;
+#pragma unroll
+            for (int m = 1; m < 8; ++m) {
+                const int tt = (m * k) << lts;
+                V2<T> w = tw[tt < N / 2 ? tt : tt - N / 2];
+                if (tt >= N / 2) { w.x = -w.x; w.y = -w.y; }
+                if (DIR > 0) w.y = -w.y;
+                x[m] = cmul<T>(x[m], w);
+            }
+        }
+        dft8<T, DIR>(x);
+        if (s < 2) {
+            const int j = (t - k) * 8 + k;
+            wave_lds_sync();   // the wave's reads of the previous exchange are done
+#pragma unroll
+            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m];
+            wave_lds_sync();   // and its writes of this one
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+        }
+    }
+    if (!valid) return;
+    if (STORE == STORE_GRID) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {   // outputs t + Q m
+            const int c = t + m * Q;
+            if (a.half) {
+                if (c < a.half) grid[gl * a.half + c] = x[m];
+            } else if (!a.band || is_data_row(c, 2 * a.band, N)) {
+                grid[gl * N + c] = x[m];
+            }
+        }
+    } else {
+        TIO* u = reinterpret_cast<TIO*>(a.u) + (long long)b * a.rstride + (long long)al * ndl;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int c = t + m * Q;
+            if (!is_data_row(c, ndl, N)) continue;
+            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
+            u[j] = (TIO)(uo[m] + (double)x[m].x * fac * pv[m] * a.post);
+        }
+    }
+}
+
+constexpr int kRows9L = 4;   // lines (waves) per workgroup of k_fft_rows_r9
+
+template <typename T, int DIR, int LOAD, int STORE, typename TIO>
+static int launch_rows_r9(nlf_plan* p, RowsArgs a, int batch) {
+    constexpr int N = 512;
+    a.lg = 9;
+    a.lines_per_wg = kRows9L;
+    dim3 grid((a.nlines + kRows9L - 1) / kRows9L, batch);
+    const size_t lds = ((size_t)kRows9L * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);   // <= 41 KiB
+    hipLaunchKernelGGL((k_fft_rows_r9<T, TIO, DIR, LOAD, STORE, kRows9L>), grid, dim3(kRows9L * 64), lds, p->stream, a);
+    NLF_HIP(hipGetLastError());
+    return NLF_OK;
+}
+
+// rows of 512 points of 3D grids take k_fft_rows_r9 (the moments are a 2D-only mode)
+static bool rows_r9_applies(const RowsArgs& a) { return a.n == 512 && a.dim == 3 && !a.mom_part && !a.add_u1; }
+
 // lines per workgroup of k_fft_rows_r.  Measured at 512^2 (FP64 evaluation, forward + inverse
 // FFT stages, us): one line per workgroup 20.1-20.5 + 19.9-20.2, two 20.7-20.8 + 19.0-19.2, the
 // LDS-resident rows (k_fft_rows) 22.1 + 19.7-19.8.
@@ -262,12 +419,12 @@ template <int LOAD> constexpr int rows_r_lines() { return LOAD == LOAD_RHO ? kRo
 
 template <typename T, int DIR, int LOAD, int STORE, typename TIO>
 static int launch_rows_r(nlf_plan* p, RowsArgs a, int batch) {
-    constexpr int N = 1024, kRowsRL = rows_r_lines<LOAD>();
+    constexpr int N = 1024, LPW = rows_r_lines<LOAD>();
     a.lg = 10;
-    a.lines_per_wg = kRowsRL;
-    dim3 grid((a.nlines + kRowsRL - 1) / kRowsRL, batch);
-    const size_t lds = ((size_t)kRowsRL * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);   // <= 45 KiB
-    hipLaunchKernelGGL((k_fft_rows_r<T, TIO, DIR, LOAD, STORE, kRowsRL>), grid, dim3(kRowsRL * 128), lds, p->stream, a);
+    a.lines_per_wg = LPW;
+    dim3 grid((a.nlines + LPW - 1) / LPW, batch);
+    const size_t lds = ((size_t)LPW * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);   // <= 45 KiB
+    hipLaunchKernelGGL((k_fft_rows_r<T, TIO, DIR, LOAD, STORE, LPW>), grid, dim3(LPW * 128), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
@@ -286,6 +443,7 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, ExecRowCfg::E, true>(p, a, batch);
     if (!recorder() && rows_r_applies(a)) return launch_rows_r<T, DIR, LOAD, STORE, TIO>(p, a, batch);
+    if (!recorder() && rows_r9_applies(a)) return launch_rows_r9<T, DIR, LOAD, STORE, TIO>(p, a, batch);
     if (a.n == 1024)
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, Row1024Cfg::E, Row1024Cfg::TWL, Row1024Cfg::NT>(p, a, batch);
     if (a.n <= 512) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, true>(p, a, batch);
