@@ -631,7 +631,7 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
 constexpr int kConv0rC = 8;   // columns per workgroup of k_fft_conv0r (128-byte row segments)
 
 template <typename T, int P, int C>
-__global__ void __launch_bounds__(C * (1 << (3 * P - 3))) k_fft_conv0r(ColsArgs a, ConvW cw) {
+__global__ void __launch_bounds__(C * (1 << (3 * P - 3)), 4) k_fft_conv0r(ColsArgs a, ConvW cw) {
     constexpr int LG = 3 * P, N = 1 << LG, Q = N / 8;   // line length, threads (butterflies) per line
     constexpr int PITCH = N + (N >> 3) + 1;             // padded line (one slot per 8) + 1
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -683,13 +683,18 @@ __global__ void __launch_bounds__(C * (1 << (3 * P - 3))) k_fft_conv0r(ColsArgs 
     __syncthreads();   // twiddles staged
     using Fwd = std::integral_constant<int, -1>;
     using Inv = std::integral_constant<int, 1>;
+    double e0[8];   // the multiply's row factors (a small table, read through the caches)
 #pragma unroll
     for (int s = 0; s < P; ++s) {
+        if (s + 1 == P) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) e0[m] = cw.e0[t + m * Q];
+        }
         pass(s, Fwd{});
         if (s + 1 < P) exchange(s);
     }
-    // thread t holds frequencies t + m Q: multiply by w(k) (column terms once per thread, as in
-    // k_fft_conv0; expm1 where 1 - e^{-x} would cancel)
+    // thread t holds frequencies t + m Q: multiply by w(k) (column terms once per thread, the
+    // row factor exp(-k0^2/a) from the plan's table; expm1 where 1 - e^{-x} would cancel)
     {
         const int c1 = (int)(col / cw.pitch2), c2 = (int)(col - (long long)c1 * cw.pitch2);
         const double k1 = (c1 < cw.Mr1 / 2 ? c1 : c1 - cw.Mr1) * cw.dk1;
@@ -703,7 +708,7 @@ __global__ void __launch_bounds__(C * (1 << (3 * P - 3))) k_fft_conv0r(ColsArgs 
             const double kk = k0 * k0 + q12;
             const double xx = kk * cw.inva;
             double w;
-            if (xx >= 1.0) w = (1.0 - exp(-k0 * k0 * cw.inva) * e12) / kk;
+            if (xx >= 1.0) w = (1.0 - e0[m] * e12) * rcp_newton(kk);
             else w = kk > 0.0 ? -expm1(-xx) / kk : cw.inva;
             x[m].x = (T)((double)x[m].x * w);
             x[m].y = (T)((double)x[m].y * w);
@@ -802,7 +807,7 @@ static int split_i1_t(nlf_plan* p, const void* rho, void* u) {
     ColsArgs c0{};
     c0.grid = p->grid_a; c0.gstride = p->G; c0.n = p->Mr[0]; c0.inner = (long long)p->Mr[1] * H;
     c0.nd = p->n[0]; c0.tw = p->tw_big[0];
-    ConvW cw{p->Mr[0], p->Mr[1], p->Mr[2], H, 0, 0, 0, 1.0 / p->split_a};
+    ConvW cw{p->Mr[0], p->Mr[1], p->Mr[2], H, 0, 0, 0, 1.0 / p->split_a, p->conv_e0};
     cw.dk0 = 2.0 * 3.14159265358979323846 / (p->Mr[0] * p->h[0]);
     cw.dk1 = 2.0 * 3.14159265358979323846 / (p->Mr[1] * p->h[1]);
     cw.dk2 = 2.0 * 3.14159265358979323846 / (p->Mr[2] * p->h[2]);

@@ -549,7 +549,18 @@ struct ConvW {
     int Mr0, Mr1, Mr2;
     int pitch2;            // stored columns of the innermost axis (its first pitch2 frequencies)
     double dk0, dk1, dk2, inva;
+    const double* e0;      // exp(-k0^2 / a) per axis-0 frequency row (the register kernel)
 };
+
+// 1/x for normal x > 0: the hardware estimate refined by two Newton steps (within an ulp or two of
+// the quotient, not correctly rounded)
+__device__ __forceinline__ double rcp_newton(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
 
 template <typename T, int NT, int E, bool TWL>
 __global__ void __launch_bounds__(NT) k_fft_conv0(ColsArgs a, ConvW cw) {

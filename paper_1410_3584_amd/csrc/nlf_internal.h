@@ -92,6 +92,7 @@ struct nlf_plan {
     // split evaluation (3D Coulomb): I1 by this plan's FFTs, I2 by the ball plan `sub`
     int split = 0;
     double split_a = 0.0, split_P2 = 0.0;
+    double* conv_e0 = nullptr;   // split: exp(-k0^2 / a) per axis-0 row of the padded grid (length Mr[0])
     int deterministic = 0;      // one work item per gather tile, plain stores; 3D plane-streamed interpolation
     int check_finite = 0;       // nlf_potential / nlf_type2 read the non-finite flag before returning
     int* nf_flag = nullptr;     // device: set to 1 by the density load pass on a NaN / Inf value

@@ -347,6 +347,15 @@ static int build_split(nlf_plan* p, const nlf_box* box, int kernel, const nlf_op
         }
         p->tw_t1[i] = p->tw_big[i];
     }
+    {   // the multiply's axis-0 factor exp(-k0^2 / a), k0 the centred frequency of row r
+        std::vector<double> e0(p->Mr[0]);
+        const double dk0 = 2.0 * 3.14159265358979323846 / (p->Mr[0] * p->h[0]);
+        for (int r = 0; r < p->Mr[0]; ++r) {
+            const double k0 = (r < p->Mr[0] / 2 ? r : r - p->Mr[0]) * dk0;
+            e0[r] = std::exp(-k0 * k0 / p->split_a);
+        }
+        NLF_TRY(upload(p, (void**)&p->conv_e0, e0.data(), e0.size() * sizeof(double)));
+    }
     NLF_TRY(dev_alloc(p, (void**)&p->mom, (size_t)p->batch * 4 * sizeof(double)));
     p->red_bytes = (size_t)p->batch * 1024 * 8 * sizeof(double);
     NLF_TRY(dev_alloc(p, (void**)&p->red, p->red_bytes));
