@@ -628,7 +628,10 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
 // the inverse transform's first inputs: the multiply by w and both transforms share registers, and
 // LDS carries only the 2 (P - 1) exchanges, instead of a read and a write per pass plus the staging
 // of the load, the multiply and the store.  C columns per workgroup, 64 n / 512 threads each.
-constexpr int kConv0rC = 8;   // columns per workgroup of k_fft_conv0r (128-byte row segments)
+// Measured at 256^3 (split potential, ms, FP64 / FP32): C = 8 2.295 / 1.205, C = 4 2.26 / 1.18.
+// Tried and not kept: the passes' twiddles staged as [pass][m][k] (no LDS bank conflicts on the
+// twiddle reads, 9 KiB instead of 4 KiB of LDS): 2.41 / 1.38, in every register-resident kernel.
+constexpr int kConv0rC = 4;   // columns per workgroup of k_fft_conv0r (64-byte row segments)
 
 template <typename T, int P, int C>
 __global__ void __launch_bounds__(C * (1 << (3 * P - 3)), 4) k_fft_conv0r(ColsArgs a, ConvW cw) {
