@@ -264,13 +264,19 @@ __global__ void __launch_bounds__(L * 128) k_fft_rows_r(RowsArgs a) {
 // the rest) and the band of a split's ball (only |f| < band read or written).
 __device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
+// LDS of k_fft_rows_r9: L scalar lines of 512 + 64 + 1 entries, then the half twiddle table
+template <typename T, int L> constexpr size_t rows_r9_tw_offset() { return ((size_t)L * 577 * sizeof(T) + 15) / 16 * 16; }
+template <typename T, int L> constexpr size_t rows_r9_lds() { return rows_r9_tw_offset<T, L>() + 256 * 2 * sizeof(T); }
+
 template <typename T, typename TIO, int DIR, int LOAD, int STORE, int L>
 __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
     constexpr int LG = 9, N = 1 << LG, Q = N / 8;
     constexpr int PITCH = N + (N >> 3) + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    V2<T>* tw = buf + L * PITCH;   // half twiddle table
+    // the exchanges move the real and the imaginary parts in turn through a line of scalars (half
+    // the LDS of a complex line, so twice the resident waves)
+    T* buf = reinterpret_cast<T*>(smem_raw);
+    V2<T>* tw = reinterpret_cast<V2<T>*>(smem_raw + rows_r9_tw_offset<T, L>());   // half twiddle table
     const int tid = threadIdx.x;
     const int l = tid >> 6, t = tid & 63;
     const int b = blockIdx.y;
@@ -288,25 +294,26 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
     }
     V2<T>* grid = reinterpret_cast<V2<T>*>(a.grid) + (long long)b * a.gstride;
     V2<T> x[8];
+    // mapped modes: the data line is half the oversampled line (256 of 512 points), so the data
+    // positions t + 64 m are those of m = 0, 1 (data index c + 128) and m = 6, 7 (c - 384)
+    constexpr int DM[4] = {0, 1, 6, 7};
+    auto data_j = [&](int m) { const int c = t + m * Q; return m < 2 ? c + N / 4 : c - 3 * N / 4; };
     if (LOAD == LOAD_RHO) {
         const TIO* rho = reinterpret_cast<const TIO*>(a.rho) + (long long)b * a.rstride + (long long)al * ndl;
-        double rv[8], dv[8];
+        double rv[4], dv[4];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int c = t + m * Q;
-            rv[m] = 0.0;
-            dv[m] = 0.0;
-            if (valid && is_data_row(c, ndl, N)) {   // oversampled position c holds data index j
-                const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
-                rv[m] = (double)rho[j];
-                dv[m] = a.dec2[j];
-            }
+        for (int d = 0; d < 4; ++d) {
+            const int j = data_j(DM[d]);
+            rv[d] = valid ? (double)rho[j] : 0.0;
+            dv[d] = a.dec2[j];
         }
         bool bad = false;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            bad = bad || !isfinite(rv[m]);
-            x[m] = mk<T>((T)(rv[m] * fac * dv[m]), 0);
+        for (int m = 0; m < 8; ++m) x[m] = mk<T>(0, 0);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            bad = bad || !isfinite(rv[d]);
+            x[DM[d]].x = (T)(rv[d] * fac * dv[d]);
         }
         if (a.nonfinite && bad) atomicOr(a.nonfinite, 1);
     } else if (a.half) {
@@ -327,24 +334,15 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
             x[m] = (valid && (!a.band || is_data_row(c, 2 * a.band, N))) ? grid[gl * N + c] : mk<T>(0, 0);
         }
     }
-    // STORE_U: the epilogue's per-element factors (and the values added to), loaded before the transform
-    double pv[8], uo[8];
-    if (STORE == STORE_U) {
+    // STORE_U: the values added to, loaded before the transform
+    double uo[4] = {0.0, 0.0, 0.0, 0.0};
+    if (STORE == STORE_U && a.accum && valid) {
         const TIO* u = reinterpret_cast<const TIO*>(a.u) + (long long)b * a.rstride + (long long)al * ndl;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int c = t + m * Q;
-            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
-            pv[m] = 0.0;
-            uo[m] = 0.0;
-            if (valid && is_data_row(c, ndl, N)) {
-                pv[m] = a.dec2[j];
-                if (a.accum) uo[m] = (double)u[j];
-            }
-        }
+        for (int d = 0; d < 4; ++d) uo[d] = (double)u[data_j(DM[d])];
     }
     for (int i = tid; i < N / 2; i += L * 64) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
-    V2<T>* line = buf + l * PITCH;
+    T* line = buf + l * PITCH;
     __syncthreads();   // twiddles staged; from here on each wave works alone
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -365,10 +363,16 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
             const int j = (t - k) * 8 + k;
             wave_lds_sync();   // the wave's reads of the previous exchange are done
 #pragma unroll
-            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m];
+            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m].x;
             wave_lds_sync();   // and its writes of this one
 #pragma unroll
-            for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+            for (int m = 0; m < 8; ++m) x[m].x = line[lpad<true>(t + m * Q)];
+            wave_lds_sync();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m].y;
+            wave_lds_sync();
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m].y = line[lpad<true>(t + m * Q)];
         }
     }
     if (!valid) return;
@@ -385,16 +389,17 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
     } else {
         TIO* u = reinterpret_cast<TIO*>(a.u) + (long long)b * a.rstride + (long long)al * ndl;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const int c = t + m * Q;
-            if (!is_data_row(c, ndl, N)) continue;
-            const int j = (c < ndl / 2) ? c + ndl / 2 : c - (N - ndl / 2);
-            u[j] = (TIO)(uo[m] + (double)x[m].x * fac * pv[m] * a.post);
+        for (int d = 0; d < 4; ++d) {
+            const int j = data_j(DM[d]);
+            u[j] = (TIO)(uo[d] + (double)x[DM[d]].x * fac * a.dec2[j] * a.post);
         }
     }
 }
 
-constexpr int kRows9L = 4;   // lines (waves) per workgroup of k_fft_rows_r9
+// lines (waves) per workgroup of k_fft_rows_r9.  Measured at 256^3 (FP64 split potential, the
+// four row passes, us): complex exchanges 117 + 113 + 102 + 133, the real and imaginary parts in
+// turn (7 resident workgroups instead of 3) 85 + 82 + 81 + 114.
+constexpr int kRows9L = 4;
 
 template <typename T, int DIR, int LOAD, int STORE, typename TIO>
 static int launch_rows_r9(nlf_plan* p, RowsArgs a, int batch) {
@@ -402,14 +407,18 @@ static int launch_rows_r9(nlf_plan* p, RowsArgs a, int batch) {
     a.lg = 9;
     a.lines_per_wg = kRows9L;
     dim3 grid((a.nlines + kRows9L - 1) / kRows9L, batch);
-    const size_t lds = ((size_t)kRows9L * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);   // <= 41 KiB
+    static_assert(N + (N >> 3) + 1 == 577, "the LDS layout of k_fft_rows_r9");
+    const size_t lds = rows_r9_lds<T, kRows9L>();   // <= 23 KiB
     hipLaunchKernelGGL((k_fft_rows_r9<T, TIO, DIR, LOAD, STORE, kRows9L>), grid, dim3(kRows9L * 64), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
 
-// rows of 512 points of 3D grids take k_fft_rows_r9 (the moments are a 2D-only mode)
-static bool rows_r9_applies(const RowsArgs& a) { return a.n == 512 && a.dim == 3 && !a.mom_part && !a.add_u1; }
+// rows of 512 points of 3D grids take k_fft_rows_r9 (the moments are a 2D-only mode; in the mapped
+// modes the data line must be half the line)
+static bool rows_r9_applies(const RowsArgs& a, bool mapped) {
+    return a.n == 512 && a.dim == 3 && !a.mom_part && !a.add_u1 && (!mapped || a.nd[2] == 256);
+}
 
 // lines per workgroup of k_fft_rows_r.  Measured at 512^2 (FP64 evaluation, forward + inverse
 // FFT stages, us): one line per workgroup 20.1-20.5 + 19.9-20.2, two 20.7-20.8 + 19.0-19.2, the
@@ -443,7 +452,7 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, ExecRowCfg::E, true>(p, a, batch);
     if (!recorder() && rows_r_applies(a)) return launch_rows_r<T, DIR, LOAD, STORE, TIO>(p, a, batch);
-    if (!recorder() && rows_r9_applies(a)) return launch_rows_r9<T, DIR, LOAD, STORE, TIO>(p, a, batch);
+    if (!recorder() && rows_r9_applies(a, LOAD == LOAD_RHO || STORE == STORE_U)) return launch_rows_r9<T, DIR, LOAD, STORE, TIO>(p, a, batch);
     if (a.n == 1024)
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, Row1024Cfg::E, Row1024Cfg::TWL, Row1024Cfg::NT>(p, a, batch);
     if (a.n <= 512) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, true>(p, a, batch);
@@ -630,7 +639,10 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
 // of the load, the multiply and the store.  C columns per workgroup, 64 n / 512 threads each.
 // Measured at 256^3 (split potential, ms, FP64 / FP32): C = 8 2.295 / 1.205, C = 4 2.26 / 1.18.
 // Tried and not kept: the passes' twiddles staged as [pass][m][k] (no LDS bank conflicts on the
-// twiddle reads, 9 KiB instead of 4 KiB of LDS): 2.41 / 1.38, in every register-resident kernel.
+// twiddle reads, 9 KiB instead of 4 KiB of LDS): 2.41 / 1.38, in every register-resident kernel;
+// the real and imaginary parts exchanged in turn through half the LDS (as k_fft_rows_r9 does, more
+// resident workgroups but twice the barriers): this kernel 421 -> 445 us, the 512-point columns
+// unchanged.
 constexpr int kConv0rC = 4;   // columns per workgroup of k_fft_conv0r (64-byte row segments)
 
 template <typename T, int P, int C>
