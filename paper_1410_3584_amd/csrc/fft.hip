@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
     const int o = blockIdx.y;
     const long long go = a.outer_mapped ? dmap(o, a.outer_nd, a.outer_Mr) : o;
     V2<T>* base = reinterpret_cast<V2<T>*>(a.grid) + (long long)blockIdx.z * a.gstride + go * (long long)N * a.inner +
-                  (long long)cb * C + c;
+                  band_col(a, cb) + c;   // consecutive blocks of C columns, or the blocks of a band
     V2<T> x[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -595,7 +595,9 @@ static int launch_cols_r(nlf_plan* p, ColsArgs a, int outer, int batch) {
     constexpr int C = cols_r_c<LG>(), N = 1 << LG;
     a.lg = LG;
     a.C = C;
-    a.ncb = (int)(a.inner / C);
+    if (a.bc2 && (a.bc2 % C || 2 * a.bc2 > (a.bc1 ? a.Mr2 : a.inner) || (a.bc1 && 2 * a.bc1 > a.Mr1)))
+        return set_error(NLF_EINVAL, "column band %d/%d does not fit the grid", a.bc1, a.bc2);
+    a.ncb = a.bc2 ? (a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / C) : (int)(a.inner / C);
     dim3 grid(a.ncb, outer, batch);
     const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);
     static std::mutex attr_mu;
@@ -617,10 +619,14 @@ template <typename T, int DIR, bool LP, bool SP>
 static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_cols_cfg<T, DIR, LP, SP, ExecColCfg::NT, ExecColCfg::E, true>(p, a, outer, batch);
-    // lines in registers (not for the band columns of a split's ball; never recorded)
-    if (!recorder() && !a.bc2) {
-        if (a.n == 512 && a.inner % cols_r_c<9>() == 0) return launch_cols_r<T, DIR, LP, SP, 9>(p, a, outer, batch);
-        if (a.n == 1024 && a.inner % cols_r_c<10>() == 0) return launch_cols_r<T, DIR, LP, SP, 10>(p, a, outer, batch);
+    // lines in registers (also the band columns of a split's ball, when the band is whole blocks:
+    // measured at 256^3, the ball's four band passes 60 + 27 + 28 + 59 us in LDS, 40 + 19 + 20 + 40
+    // in registers; never recorded)
+    if (!recorder()) {
+        if (a.n == 512 && a.inner % cols_r_c<9>() == 0 && a.bc2 % cols_r_c<9>() == 0)
+            return launch_cols_r<T, DIR, LP, SP, 9>(p, a, outer, batch);
+        if (a.n == 1024 && a.inner % cols_r_c<10>() == 0 && a.bc2 % cols_r_c<10>() == 0)
+            return launch_cols_r<T, DIR, LP, SP, 10>(p, a, outer, batch);
     }
     if (a.n <= 512)
         return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E, true>(p, a, outer, batch);
