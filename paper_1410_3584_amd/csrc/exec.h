@@ -48,6 +48,13 @@ enum TaskKind : int {
 
 constexpr int kTaskArgBytes = 1024;
 constexpr int kExecThreads = 256;
+// Register budget of k_exec (launch bound: waves per SIMD) and resident executor workgroups per
+// CU.  The executor holds the registers of its largest body (376 VGPRs at one wave per SIMD).
+// Measured on 64 batched 2D ground states (ground states/s): 1/1 20.9, 2/1 20.7, 2/2 18.3,
+// 4/2 14.0, 4/4 9.5: the grid barriers of more workgroups and the spills of a smaller budget cost
+// more than the occupancy gains.
+constexpr int kExecWavesPerEU = 1;
+constexpr int kExecPerCU = 1;
 
 struct TaskRec {
     int kind;

@@ -1312,7 +1312,7 @@ __device__ __forceinline__ void exec_stall(const ExecProg& P, const ExecStage& S
         }
 }
 
-__global__ void __launch_bounds__(kExecThreads, 1) k_exec(ExecProg P) {
+__global__ void __launch_bounds__(kExecThreads, kExecWavesPerEU) k_exec(ExecProg P) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long passed = 0;
     int used = 0;   // outer steps of the earlier stage
@@ -1527,9 +1527,9 @@ static int exec_batch(int count, nlf_plan* const plans[], const nlf_phys* const 
             rc = set_error(NLF_EHIP, "the executor does not fit a CU (%zu bytes of LDS)", lds);
             break;
         }
-        // one workgroup per CU: a grid barrier costs its workgroups' fences (each an L2 write-back on
-        // this multi-XCD device), and more workgroups made every barrier slower than they saved
-        const int nwg = std::max(8, cus / 8 * 8);
+        // kExecPerCU workgroups per CU (fewer if fewer fit): a grid barrier costs its workgroups'
+        // fences (each an L2 write-back on this multi-XCD device) and polls
+        const int nwg = std::max(8, cus / 8 * 8) * std::min(per_cu, kExecPerCU);
         void* args[] = {&P};
         if (hipLaunchCooperativeKernel((const void*)&k_exec, dim3(nwg), dim3(kExecThreads), args, (unsigned)lds, st0) !=
             hipSuccess) {
