@@ -513,8 +513,7 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
 // columns per workgroup, C n / 8 threads.
 template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int LG, int C>
 __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) {
-    static_assert(LG % 3 == 0 || LG % 3 == 1, "radix 8 passes after at most one radix-2 pass");
-    constexpr int N = 1 << LG, Q = N / 8, R2 = LG % 3;   // R2: a first radix-2 pass
+    constexpr int N = 1 << LG, Q = N / 8, R2 = LG % 3;   // R2: a first radix-2 (1) or radix-4 (2) pass
     constexpr int PITCH = N + (N >> 3) + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
@@ -538,7 +537,7 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
     for (int i = tid; i < N / 2; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
     V2<T>* line = buf + c * PITCH;
     __syncthreads();   // twiddles staged
-    if constexpr (R2) {
+    if constexpr (R2 == 1) {
         // pass 0, radix 2 (p = 1): butterfly i = t + Q m (m < 4) takes x[i], x[i + n/2] and writes
         // positions 2 i and 2 i + 1
 #pragma unroll
@@ -547,6 +546,22 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
             const int i = t + m * Q;
             line[lpad<true>(2 * i)] = cadd<T>(u, v);
             line[lpad<true>(2 * i + 1)] = csub<T>(u, v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = line[lpad<true>(t + m * Q)];
+    } else if constexpr (R2 == 2) {
+        // pass 0, radix 4 (p = 1): butterfly i = t + Q m (m < 2) takes x[i + k n/4] (registers
+        // m + 2 k) and writes positions 4 i + r
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            V2<T> a0 = x[m], a1 = x[m + 2], a2 = x[m + 4], a3 = x[m + 6];
+            dft4<T, DIR>(a0, a1, a2, a3);
+            const int i = t + m * Q;
+            line[lpad<true>(4 * i)] = a0;
+            line[lpad<true>(4 * i + 1)] = a1;
+            line[lpad<true>(4 * i + 2)] = a2;
+            line[lpad<true>(4 * i + 3)] = a3;
         }
         __syncthreads();
 #pragma unroll
@@ -587,8 +602,9 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
     }
 }
 
-// 512 threads per workgroup: 4 columns of 1024 points (64-byte row segments) or 8 of 512 (128 bytes)
-template <int LG> constexpr int cols_r_c() { return LG == 10 ? 4 : 8; }
+// 512 threads per workgroup: 4 columns of 1024 points (64-byte row segments) or 8 of 512 (128
+// bytes); 256 threads for the shorter columns: 8 of 256, 16 of 128, 32 of 64 points
+template <int LG> constexpr int cols_r_c() { return LG == 10 ? 4 : LG == 9 ? 8 : 2048 >> LG; }
 
 template <typename T, int DIR, bool LP, bool SP, int LG>
 static int launch_cols_r(nlf_plan* p, ColsArgs a, int outer, int batch) {
@@ -627,6 +643,11 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
             return launch_cols_r<T, DIR, LP, SP, 9>(p, a, outer, batch);
         if (a.n == 1024 && a.inner % cols_r_c<10>() == 0 && a.bc2 % cols_r_c<10>() == 0)
             return launch_cols_r<T, DIR, LP, SP, 10>(p, a, outer, batch);
+        // 64- to 256-point columns, where the blocks of C columns still fill the device
+        auto fills = [&](int c) { return !a.bc2 && a.inner % c == 0 && (a.inner / c) * outer * (long long)batch >= 256; };
+        if (a.n == 256 && fills(cols_r_c<8>())) return launch_cols_r<T, DIR, LP, SP, 8>(p, a, outer, batch);
+        if (a.n == 128 && fills(cols_r_c<7>())) return launch_cols_r<T, DIR, LP, SP, 7>(p, a, outer, batch);
+        if (a.n == 64 && fills(cols_r_c<6>())) return launch_cols_r<T, DIR, LP, SP, 6>(p, a, outer, batch);
     }
     if (a.n <= 512)
         return launch_cols_cfg<T, DIR, LP, SP, ColSmallCfg::NT, ColSmallCfg::E, true>(p, a, outer, batch);
