@@ -254,48 +254,62 @@ __global__ void __launch_bounds__(L * 128) k_fft_rows_r(RowsArgs a) {
     }
 }
 
-// Contiguous-axis pass of 512-point lines of a 3D grid with the lines in registers: one wave per
-// line (lane t holds the elements t + 64 m), so the exchanges between the three radix-8 passes
-// stay inside the wave and need no workgroup barrier, only the wave's own LDS writes to have
-// completed.  L lines (waves) per workgroup share the staged twiddle table.  The fused modes are
-// those of fft_rows_body for 3D lines: LOAD_RHO (density row with the precorrection), STORE_U (the
-// data positions of the real part with the postcorrection, optionally added to u), the Hermitian
-// half of a transform of real data (STORE_GRID writes the first `half` outputs, LOAD_GRID rebuilds
-// the rest) and the band of a split's ball (only |f| < band read or written).
+// Contiguous-axis pass of lines of N = 64 to 512 points with the lines in registers, the lines of
+// a wave inside the wave: lane (l, t), l < 512 / N, holds the elements t + m N/8 of line l, so the
+// exchanges between the passes (a first radix-2 or radix-4 pass when log2 N is not a multiple of 3,
+// then radix-8 passes) stay inside the wave and need no workgroup barrier, only the wave's own LDS
+// writes to have completed.  The exchanges move the real and the imaginary parts in turn through
+// lines of scalars (half the LDS of complex lines, so more resident workgroups).  W waves per
+// workgroup share the staged twiddle table.  The fused modes are those of fft_rows_body: LOAD_RHO
+// (density row with the precorrection), STORE_U (the data positions of the real part with the
+// postcorrection, optionally added to u), the Hermitian half of a transform of real data (STORE_GRID
+// writes the first `half` outputs, LOAD_GRID rebuilds the rest) and the band of a split's ball (only
+// |f| < band read or written).  The mapped modes take data lines of half the line length.
 __device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-// LDS of k_fft_rows_r9: L scalar lines of 512 + 64 + 1 entries, then the half twiddle table
-template <typename T, int L> constexpr size_t rows_r9_tw_offset() { return ((size_t)L * 577 * sizeof(T) + 15) / 16 * 16; }
-template <typename T, int L> constexpr size_t rows_r9_lds() { return rows_r9_tw_offset<T, L>() + 256 * 2 * sizeof(T); }
+// LDS of k_fft_rows_rw: per wave 512/N scalar lines of N + N/8 + 1 entries, then the half twiddle table
+template <typename T, int LG, int W> constexpr size_t rows_rw_tw_offset() {
+    return ((size_t)W * (512 >> LG) * ((1 << LG) + (1 << (LG - 3)) + 1) * sizeof(T) + 15) / 16 * 16;
+}
+template <typename T, int LG, int W> constexpr size_t rows_rw_lds() {
+    return rows_rw_tw_offset<T, LG, W>() + (size_t)(1 << (LG - 1)) * 2 * sizeof(T);
+}
 
-template <typename T, typename TIO, int DIR, int LOAD, int STORE, int L>
-__global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
-    constexpr int LG = 9, N = 1 << LG, Q = N / 8;
+template <typename T, typename TIO, int DIR, int LOAD, int STORE, int LG, int W>
+__global__ void __launch_bounds__(W * 64) k_fft_rows_rw(RowsArgs a) {
+    constexpr int N = 1 << LG, Q = N / 8, LPW = 64 / Q, R2 = LG % 3, NP = LG / 3;
     constexpr int PITCH = N + (N >> 3) + 1;
+    static_assert(LG >= 6 && LG <= 9, "64 to 512 points");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    // the exchanges move the real and the imaginary parts in turn through a line of scalars (half
-    // the LDS of a complex line, so twice the resident waves)
     T* buf = reinterpret_cast<T*>(smem_raw);
-    V2<T>* tw = reinterpret_cast<V2<T>*>(smem_raw + rows_r9_tw_offset<T, L>());   // half twiddle table
+    V2<T>* tw = reinterpret_cast<V2<T>*>(smem_raw + rows_rw_tw_offset<T, LG, W>());   // half twiddle table
     const int tid = threadIdx.x;
-    const int l = tid >> 6, t = tid & 63;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int t = lane % Q;
     const int b = blockIdx.y;
-    const int al = blockIdx.x * L + l;   // data line j0 nd1 + j1 when mapped
+    const int al = (blockIdx.x * W + wv) * LPW + lane / Q;   // data line (j0 nd1 + j1 in 3D) when mapped
     const bool valid = al < a.nlines;
     constexpr bool mapped = (LOAD == LOAD_RHO) || (STORE == STORE_U);
-    const int ndl = a.nd[2];
+    const int last = a.dim - 1;
+    const int ndl = a.nd[last];
+    const double* decl = (a.dim == 2) ? a.dec1 : a.dec2;
     long long gl = al;
     double fac = 1.0;
     if (mapped) {
         const int la = valid ? al : 0;
-        const int j0 = la / a.nd[1], j1 = la - j0 * a.nd[1];
-        gl = (long long)dmap(j0, a.nd[0], a.Mr[0]) * a.Mr[1] + dmap(j1, a.nd[1], a.Mr[1]);
-        fac = a.dec0[j0] * a.dec1[j1];
+        if (a.dim == 2) {
+            gl = dmap(la, a.nd[0], a.Mr[0]);
+            fac = a.dec0[la];
+        } else {
+            const int j0 = la / a.nd[1], j1 = la - j0 * a.nd[1];
+            gl = (long long)dmap(j0, a.nd[0], a.Mr[0]) * a.Mr[1] + dmap(j1, a.nd[1], a.Mr[1]);
+            fac = a.dec0[j0] * a.dec1[j1];
+        }
     }
     V2<T>* grid = reinterpret_cast<V2<T>*>(a.grid) + (long long)b * a.gstride;
     V2<T> x[8];
-    // mapped modes: the data line is half the oversampled line (256 of 512 points), so the data
-    // positions t + 64 m are those of m = 0, 1 (data index c + 128) and m = 6, 7 (c - 384)
+    // mapped modes: the data line is half the line, so the data positions t + Q m are those of
+    // m = 0, 1 (data index c + N/4) and m = 6, 7 (c - 3N/4)
     constexpr int DM[4] = {0, 1, 6, 7};
     auto data_j = [&](int m) { const int c = t + m * Q; return m < 2 ? c + N / 4 : c - 3 * N / 4; };
     if (LOAD == LOAD_RHO) {
@@ -305,7 +319,7 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
         for (int d = 0; d < 4; ++d) {
             const int j = data_j(DM[d]);
             rv[d] = valid ? (double)rho[j] : 0.0;
-            dv[d] = a.dec2[j];
+            dv[d] = decl[j];
         }
         bool bad = false;
 #pragma unroll
@@ -341,14 +355,60 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) uo[d] = (double)u[data_j(DM[d])];
     }
-    for (int i = tid; i < N / 2; i += L * 64) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
-    T* line = buf + l * PITCH;
+    for (int i = tid; i < N / 2; i += W * 64) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    T* line = buf + (wv * LPW + lane / Q) * PITCH;
     __syncthreads();   // twiddles staged; from here on each wave works alone
+    // y[m] goes to position pos[m] of the line; the next pass reads t + Q m
+    auto exchange = [&](const V2<T> (&y)[8], const int (&pos)[8]) {
+        wave_lds_sync();   // the wave's reads of the previous exchange are done
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const int lgp = 3 * s, p = 1 << lgp, k = t & (p - 1);
-        if (s > 0) {
-            const int lts = LG - 3 - lgp;
+        for (int m = 0; m < 8; ++m) line[lpad<true>(pos[m])] = y[m].x;
+        wave_lds_sync();   // and its writes of this one
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m].x = line[lpad<true>(t + m * Q)];
+        wave_lds_sync();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) line[lpad<true>(pos[m])] = y[m].y;
+        wave_lds_sync();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m].y = line[lpad<true>(t + m * Q)];
+    };
+    if constexpr (R2 == 1) {   // radix 2, p = 1: butterfly i = t + Q m (m < 4) on x[i], x[i + N/2]
+        V2<T> y[8];
+        int pos[8];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int i = t + m * Q;
+            y[m] = cadd<T>(x[m], x[m + 4]);
+            y[m + 4] = csub<T>(x[m], x[m + 4]);
+            pos[m] = 2 * i;
+            pos[m + 4] = 2 * i + 1;
+        }
+        exchange(y, pos);
+    } else if constexpr (R2 == 2) {   // radix 4, p = 1: butterfly i = t + Q m (m < 2) on x[i + k N/4]
+        V2<T> y[8];
+        int pos[8];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            V2<T> a0 = x[m], a1 = x[m + 2], a2 = x[m + 4], a3 = x[m + 6];
+            dft4<T, DIR>(a0, a1, a2, a3);
+            const int i = t + m * Q;
+            y[m] = a0;
+            y[m + 2] = a1;
+            y[m + 4] = a2;
+            y[m + 6] = a3;
+            pos[m] = 4 * i;
+            pos[m + 2] = 4 * i + 1;
+            pos[m + 4] = 4 * i + 2;
+            pos[m + 6] = 4 * i + 3;
+        }
+        exchange(y, pos);
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+        const int lgp = R2 + 3 * s, p = 1 << lgp, k = t & (p - 1);
+        if (p > 1) {
+            const int lts = LG - 3 - lgp;   // twiddle stride N / (8 p)
 #pragma unroll
             for (int m = 1; m < 8; ++m) {
                 const int tt = (m * k) << lts;
@@ -359,20 +419,16 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
             }
         }
         dft8<T, DIR>(x);
-        if (s < 2) {
+        if (s + 1 < NP) {
             const int j = (t - k) * 8 + k;
-            wave_lds_sync();   // the wave's reads of the previous exchange are done
+            V2<T> y[8];
+            int pos[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m].x;
-            wave_lds_sync();   // and its writes of this one
-#pragma unroll
-            for (int m = 0; m < 8; ++m) x[m].x = line[lpad<true>(t + m * Q)];
-            wave_lds_sync();
-#pragma unroll
-            for (int m = 0; m < 8; ++m) line[lpad<true>(j + m * p)] = x[m].y;
-            wave_lds_sync();
-#pragma unroll
-            for (int m = 0; m < 8; ++m) x[m].y = line[lpad<true>(t + m * Q)];
+            for (int m = 0; m < 8; ++m) {
+                y[m] = x[m];
+                pos[m] = j + m * p;
+            }
+            exchange(y, pos);
         }
     }
     if (!valid) return;
@@ -391,33 +447,33 @@ __global__ void __launch_bounds__(L * 64) k_fft_rows_r9(RowsArgs a) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const int j = data_j(DM[d]);
-            u[j] = (TIO)(uo[d] + (double)x[DM[d]].x * fac * a.dec2[j] * a.post);
+            u[j] = (TIO)(uo[d] + (double)x[DM[d]].x * fac * decl[j] * a.post);
         }
     }
 }
 
-// lines (waves) per workgroup of k_fft_rows_r9.  Measured at 256^3 (FP64 split potential, the
-// four row passes, us): complex exchanges 117 + 113 + 102 + 133, the real and imaginary parts in
-// turn (7 resident workgroups instead of 3) 85 + 82 + 81 + 114.
-constexpr int kRows9L = 4;
+// waves per workgroup of k_fft_rows_rw.  Measured at 256^3 (FP64 split potential, the four
+// 512-point row passes, us): complex exchanges 117 + 113 + 102 + 133, the real and imaginary parts
+// in turn (7 resident workgroups instead of 3) 85 + 82 + 81 + 114.
+constexpr int kRowsW = 4;
 
-template <typename T, int DIR, int LOAD, int STORE, typename TIO>
-static int launch_rows_r9(nlf_plan* p, RowsArgs a, int batch) {
-    constexpr int N = 512;
-    a.lg = 9;
-    a.lines_per_wg = kRows9L;
-    dim3 grid((a.nlines + kRows9L - 1) / kRows9L, batch);
-    static_assert(N + (N >> 3) + 1 == 577, "the LDS layout of k_fft_rows_r9");
-    const size_t lds = rows_r9_lds<T, kRows9L>();   // <= 23 KiB
-    hipLaunchKernelGGL((k_fft_rows_r9<T, TIO, DIR, LOAD, STORE, kRows9L>), grid, dim3(kRows9L * 64), lds, p->stream, a);
+template <typename T, int DIR, int LOAD, int STORE, typename TIO, int LG>
+static int launch_rows_rw(nlf_plan* p, RowsArgs a, int batch) {
+    constexpr int LPWG = kRowsW * (512 >> LG);   // lines per workgroup
+    a.lg = LG;
+    a.lines_per_wg = LPWG;
+    dim3 grid((a.nlines + LPWG - 1) / LPWG, batch);
+    const size_t lds = rows_rw_lds<T, LG, kRowsW>();   // <= 23 KiB
+    hipLaunchKernelGGL((k_fft_rows_rw<T, TIO, DIR, LOAD, STORE, LG, kRowsW>), grid, dim3(kRowsW * 64), lds, p->stream, a);
     NLF_HIP(hipGetLastError());
     return NLF_OK;
 }
 
-// rows of 512 points of 3D grids take k_fft_rows_r9 (the moments are a 2D-only mode; in the mapped
-// modes the data line must be half the line)
-static bool rows_r9_applies(const RowsArgs& a, bool mapped) {
-    return a.n == 512 && a.dim == 3 && !a.mom_part && !a.add_u1 && (!mapped || a.nd[2] == 256);
+// rows of 64 to 512 points take k_fft_rows_rw: not the 2D moments or u1 terms, and in the mapped
+// modes only data lines of half the line
+static bool rows_rw_applies(const RowsArgs& a, bool mapped) {
+    return a.n >= 64 && a.n <= 512 && (a.dim == 2 || a.dim == 3) && !a.mom_part && !a.add_u1 &&
+           (!mapped || 2 * a.nd[a.dim - 1] == a.n);
 }
 
 // lines per workgroup of k_fft_rows_r.  Measured at 512^2 (FP64 evaluation, forward + inverse
@@ -452,7 +508,15 @@ static int launch_rows(nlf_plan* p, RowsArgs a, int batch) {
     if (recorder() && a.n <= 512)   // recorded for the persistent executor
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, ExecRowCfg::E, true>(p, a, batch);
     if (!recorder() && rows_r_applies(a)) return launch_rows_r<T, DIR, LOAD, STORE, TIO>(p, a, batch);
-    if (!recorder() && rows_r9_applies(a, LOAD == LOAD_RHO || STORE == STORE_U)) return launch_rows_r9<T, DIR, LOAD, STORE, TIO>(p, a, batch);
+    if (!recorder() && rows_rw_applies(a, LOAD == LOAD_RHO || STORE == STORE_U)) {
+        switch (a.n) {
+            case 512: return launch_rows_rw<T, DIR, LOAD, STORE, TIO, 9>(p, a, batch);
+            case 256: return launch_rows_rw<T, DIR, LOAD, STORE, TIO, 8>(p, a, batch);
+            case 128: return launch_rows_rw<T, DIR, LOAD, STORE, TIO, 7>(p, a, batch);
+            case 64: return launch_rows_rw<T, DIR, LOAD, STORE, TIO, 6>(p, a, batch);
+            default: break;
+        }
+    }
     if (a.n == 1024)
         return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, Row1024Cfg::E, Row1024Cfg::TWL, Row1024Cfg::NT>(p, a, batch);
     if (a.n <= 512) return launch_rows_cfg<T, DIR, LOAD, STORE, TIO, RowCfg::E, true>(p, a, batch);
@@ -667,7 +731,7 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
 // Measured at 256^3 (split potential, ms, FP64 / FP32): C = 8 2.295 / 1.205, C = 4 2.26 / 1.18.
 // Tried and not kept: the passes' twiddles staged as [pass][m][k] (no LDS bank conflicts on the
 // twiddle reads, 9 KiB instead of 4 KiB of LDS): 2.41 / 1.38, in every register-resident kernel;
-// the real and imaginary parts exchanged in turn through half the LDS (as k_fft_rows_r9 does, more
+// the real and imaginary parts exchanged in turn through half the LDS (as k_fft_rows_rw does, more
 // resident workgroups but twice the barriers): this kernel 421 -> 445 us, the 512-point columns
 // unchanged.
 constexpr int kConv0rC = 4;   // columns per workgroup of k_fft_conv0r (64-byte row segments)
