@@ -559,6 +559,9 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
     };
     NodeData d0{};
     fetch(d0, node_at(0), 0);
+    // the candidate index runs one block ahead of the node data it addresses, so that the data's
+    // loads do not wait for the index load's latency
+    int nxt = node_at(KC);
     auto block = [&](int base, NodeData& d) {
         const int cnt = min(KC, it.count - base);
         if (base > 0) lds_barrier();   // the previous block's products have read S
@@ -614,7 +617,8 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
         for (int c = 0; c < 8; ++c)
             *reinterpret_cast<double2*>(mine + 2 * mrow_slot(k, c)) = make_double2(row[2 * c], row[2 * c + 1]);
         lds_barrier();
-        fetch(d, node_at(base + KC), base + KC);   // the next block's (this block's weights are built)
+        fetch(d, nxt, base + KC);   // the next block's (this block's weights are built)
+        nxt = node_at(base + 2 * KC);
         if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
             constexpr int kSteps = KC / NW / 4;
             double av[kSteps], bv[kSteps];
@@ -763,6 +767,7 @@ __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long 
     };
     NodeData d0{};
     fetch(d0, node_at(0), 0);
+    int nxt = node_at(KC);   // the candidate index one block ahead of its data, as in mspread_body
     auto block = [&](int base, NodeData& d) {
         const int cnt = min(KC, it.count - base);
         if (base > 0) lds_barrier();   // the previous block's products have read SA, SB
@@ -820,7 +825,8 @@ __device__ __forceinline__ void mspread32_body(double2* __restrict__ grid, long 
 #pragma unroll
         for (int j = 0; j < 16; ++j) dst[j * KP + k] = row[j];
         lds_barrier();
-        fetch(d, node_at(base + KC), base + KC);   // the next block's (this block's weights are built)
+        fetch(d, nxt, base + KC);   // the next block's (this block's weights are built)
+        nxt = node_at(base + 2 * KC);
         if (kb < cnt) {   // rows past the count are zero: whole steps, fully unrolled
             constexpr int kSteps = KC / NW / 4;
             f4_t c0 = {0.0f, 0.0f, 0.0f, 0.0f}, c1 = c0, c2 = c0, c3 = c0;
