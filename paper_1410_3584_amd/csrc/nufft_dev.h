@@ -1311,20 +1311,23 @@ __global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict
     }
     // node data of this thread's candidate in the current block, loaded one block ahead so that
     // the loads overlap the previous block's matrix products
+    // (the candidate index one block further ahead, so that these loads do not wait for it)
     int fnode = 0;
     double fs = 0.0, fsb = 0.0;
-    auto fetch = [&](int bs) {
+    auto index_at = [&](int bs) -> int { return (bs + k < it.count) ? cand[it.start + bs + k] : 0; };
+    auto fetch = [&](int bs, int node) {
         if (bs + k < it.count) {
-            fnode = cand[it.start + bs + k];
+            fnode = node;
             if (t < kMChunk) {
-                fs = na.s[0][fnode];
+                fs = na.s[0][node];
             } else {
-                fs = na.s[1][fnode];
-                if (DIM == 3) fsb = na.s[2][fnode];
+                fs = na.s[1][node];
+                if (DIM == 3) fsb = na.s[2][node];
             }
         }
     };
-    fetch(0);
+    fetch(0, index_at(0));
+    int nxt = index_at(kMChunk);
     for (int base = 0; base < it.count; base += kMChunk) {
         const int cnt = min(kMChunk, it.count - base);
         if (base > 0) __syncthreads();   // the previous block has read W0T, W1T and nodes
@@ -1363,7 +1366,8 @@ __global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict
             for (int j = 0; j < 16; ++j) W1T[j][k] = w1[j];
         }
         __syncthreads();
-        fetch(base + kMChunk);
+        fetch(base + kMChunk, nxt);
+        nxt = index_at(base + 2 * kMChunk);
 #pragma unroll
         for (int gi = 0; gi < kMChunk / 64; ++gi) {
             const int k0 = 16 * (wv + 4 * gi);
