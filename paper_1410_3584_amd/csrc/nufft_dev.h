@@ -672,6 +672,8 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
     }
 }
 
+// (4 waves per SIMD: a bound of 5, which the LDS would admit, spills in the block loop and was
+// measured 30% slower)
 template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS, bool WT>
 __global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
@@ -1098,8 +1100,9 @@ __device__ __forceinline__ void binterp2_body(const V2<T>* __restrict__ grid, lo
     }
 }
 
+// (5 waves per SIMD where the LDS admits five workgroups per CU)
 template <typename T, int MSP, bool ITAB>
-__global__ void __launch_bounds__(256, 3) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
+__global__ void __launch_bounds__(256, Binterp2Lds<MSP>::bytes <= 32768 ? 5 : 3) k_binterp2(const V2<T>* __restrict__ grid, long long gstride,
                                                  NodeArgs na, EpiArgs ea, double qq4,
                                                  double2* __restrict__ zero, long long zero16) {
     __shared__ __align__(16) unsigned char smem[Binterp2Lds<MSP>::bytes];
@@ -1276,8 +1279,9 @@ __global__ void __launch_bounds__(256, 3) k_binterp2_32(const float2* __restrict
 // registers as the A operand, B comes from LDS.  The contraction with w0 is a 4-term dot product
 // per lane plus one lane exchange; the node's complex sum is added to its FP64 accumulator, which
 // the per-node epilogue then turns into c_k (or rhohat_k).
+// (5 waves per SIMD: 94-96 VGPRs, no spills; 4 waves were 10% slower at 256^3)
 template <typename T, int MSP, int DIM>
-__global__ void __launch_bounds__(2 * kMChunk) k_minterp(const V2<T>* __restrict__ grid, long long gstride,
+__global__ void __launch_bounds__(2 * kMChunk, 5) k_minterp(const V2<T>* __restrict__ grid, long long gstride,
                                                         double2* __restrict__ acc, long long astride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
                                                         const int* __restrict__ cand, double qq) {
