@@ -565,6 +565,19 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
     return NLF_OK;
 }
 
+// w^tt (0 <= tt < n = 2^LG) from the quarter table w^t, t < n/4, of w = e^{-2 pi i/n}:
+// w^(t + n/4) = -i w^t.  The register-resident column kernels stage only this quarter: at 1024
+// points the half table pushed a workgroup's LDS just past a half (FP64) or a quarter (FP32, and the
+// 512-point fused axis-0 kernel) of the CU's 160 KiB, one resident workgroup fewer.
+template <typename T, int LG>
+__device__ __forceinline__ V2<T> qtw(const V2<T>* tw, int tt) {
+    V2<T> w = tw[tt & ((1 << (LG - 2)) - 1)];
+    const int q = tt >> (LG - 2);
+    if (q & 1) w = mk<T>(w.y, -w.x);
+    if (q & 2) w = mk<T>(-w.x, -w.y);
+    return w;
+}
+
 // Strided-axis pass of n = 2^LG-point lines with the lines in registers, for n = 512 = 8 x 8 x 8
 // and n = 1024 = 2 x 8 x 8 x 8 (the oversampled axes of the 256^3 and 512^2 grids).  Thread t of a
 // column holds the 8 elements t + m n/8 (m = 0..7).  With a radix-2 factor, its registers m and
@@ -573,7 +586,7 @@ static int launch_cols_cfg(nlf_plan* p, ColsArgs a, int outer, int batch) {
 // their Stockham positions, the next inputs read back).  After the last pass thread t holds the
 // outputs t + m n/8, stored directly: LG/3 exchanges (3 at 1024, 2 at 512) instead of a read and a
 // write per pass plus the staging of the load and the store.  The passes are those of lds_fft
-// (radix 2 first, then radix 8); the twiddles come from the half table, w^(t + n/2) = -w^t.  C
+// (radix 2 first, then radix 8); the twiddles come from the quarter table (qtw).  C
 // columns per workgroup, C n / 8 threads.
 template <typename T, int DIR, bool LPRUNE, bool SPRUNE, int LG, int C>
 __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) {
@@ -581,7 +594,7 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
     constexpr int PITCH = N + (N >> 3) + 1;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    V2<T>* tw = buf + C * PITCH;   // half twiddle table, w^t for t < N/2
+    V2<T>* tw = buf + C * PITCH;   // quarter twiddle table, w^t for t < N/4 (qtw)
     const int tid = threadIdx.x;
     const int c = tid % C, t = tid / C;
     if (a.mom && blockIdx.x == 0 && blockIdx.y == 0) finish_moments(a, blockIdx.z, C * Q);
@@ -598,7 +611,7 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
         const int r = t + m * Q;
         x[m] = (!LPRUNE || is_data_row(r, a.nd, N)) ? base[(long long)r * a.inner] : mk<T>(0, 0);
     }
-    for (int i = tid; i < N / 2; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    for (int i = tid; i < N / 4; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
     V2<T>* line = buf + c * PITCH;
     __syncthreads();   // twiddles staged
     if constexpr (R2 == 1) {
@@ -640,9 +653,7 @@ __global__ void __launch_bounds__(C * (1 << (LG - 3))) k_fft_cols_r(ColsArgs a) 
             const int lts = LG - 3 - lgp;   // twiddle stride n / (8 p)
 #pragma unroll
             for (int m = 1; m < 8; ++m) {
-                const int tt = (m * k) << lts;
-                V2<T> w = tw[tt < N / 2 ? tt : tt - N / 2];
-                if (tt >= N / 2) { w.x = -w.x; w.y = -w.y; }
+                V2<T> w = qtw<T, LG>(tw, (m * k) << lts);
                 if (DIR > 0) w.y = -w.y;
                 x[m] = cmul<T>(x[m], w);
             }
@@ -679,7 +690,7 @@ static int launch_cols_r(nlf_plan* p, ColsArgs a, int outer, int batch) {
         return set_error(NLF_EINVAL, "column band %d/%d does not fit the grid", a.bc1, a.bc2);
     a.ncb = a.bc2 ? (a.bc1 ? 2 * a.bc1 : 1) * (2 * a.bc2 / C) : (int)(a.inner / C);
     dim3 grid(a.ncb, outer, batch);
-    const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);
+    const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 4) * sizeof(V2<T>);
     static std::mutex attr_mu;
     static bool raised = false;
     {
@@ -742,7 +753,7 @@ __global__ void __launch_bounds__(C * (1 << (3 * P - 3)), 4) k_fft_conv0r(ColsAr
     constexpr int PITCH = N + (N >> 3) + 1;             // padded line (one slot per 8) + 1
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V2<T>* buf = reinterpret_cast<V2<T>*>(smem_raw);
-    V2<T>* tw = buf + C * PITCH;                        // half twiddle table, w^t for t < N/2
+    V2<T>* tw = buf + C * PITCH;                        // quarter twiddle table, w^t for t < N/4
     const int tid = threadIdx.x;
     const int c = tid % C, t = tid / C;                 // C adjacent columns per row segment
     int cb = blockIdx.x;
@@ -756,7 +767,7 @@ __global__ void __launch_bounds__(C * (1 << (3 * P - 3)), 4) k_fft_conv0r(ColsAr
         const int r = t + m * Q;
         x[m] = is_data_row(r, a.nd, N) ? base[(long long)r * a.inner] : mk<T>(0, 0);
     }
-    for (int i = tid; i < N / 2; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
+    for (int i = tid; i < N / 4; i += C * Q) tw[i] = reinterpret_cast<const V2<T>*>(a.tw)[i];
     V2<T>* line = buf + c * PITCH;
     // one radix-8 pass on the registers: butterfly t, p = 8^s, inputs x[m] = line[t + m Q]
     auto pass = [&](int s, auto dir) {
@@ -766,9 +777,7 @@ __global__ void __launch_bounds__(C * (1 << (3 * P - 3)), 4) k_fft_conv0r(ColsAr
             const int lts = LG - 3 - 3 * s;   // twiddle stride n / (8 p)
 #pragma unroll
             for (int m = 1; m < 8; ++m) {
-                const int tt = (m * k) << lts;
-                V2<T> w = tw[tt < N / 2 ? tt : tt - N / 2];
-                if (tt >= N / 2) { w.x = -w.x; w.y = -w.y; }
+                V2<T> w = qtw<T, LG>(tw, (m * k) << lts);
                 if (DIR > 0) w.y = -w.y;
                 x[m] = cmul<T>(x[m], w);
             }
@@ -837,7 +846,7 @@ static int launch_conv0r(nlf_plan* p, ColsArgs a, ConvW cw, int batch) {
     constexpr int N = 1 << (3 * P), NT = C * N / 8;
     a.ncb = (int)(a.inner / C);
     dim3 grid(a.ncb, 1, batch);
-    const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 2) * sizeof(V2<T>);
+    const size_t lds = ((size_t)C * (N + (N >> 3) + 1) + N / 4) * sizeof(V2<T>);
     static std::mutex attr_mu;
     static bool raised = false;
     {
