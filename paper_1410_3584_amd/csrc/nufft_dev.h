@@ -630,12 +630,19 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
                 bv[q] = S[KC * 16 + off];
             }
             static_assert(kSteps % 4 == 0, "four chains");
+            if constexpr (WT) {
+                // one product chain: the FP64 matrix pipe issues at the same rate with one chain as
+                // with four, and the 24 registers saved admit a fifth wave per SIMD
 #pragma unroll
-            for (int q = 0; q < kSteps; q += 4) {
-                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 1], bv[q + 1], acc1, 0, 0, 0);
-                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 2], bv[q + 2], acc2, 0, 0, 0);
-                acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 3], bv[q + 3], acc3, 0, 0, 0);
+                for (int q = 0; q < kSteps; ++q) acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int q = 0; q < kSteps; q += 4) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 1], bv[q + 1], acc1, 0, 0, 0);
+                    acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 2], bv[q + 2], acc2, 0, 0, 0);
+                    acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q + 3], bv[q + 3], acc3, 0, 0, 0);
+                }
             }
         }
     };
@@ -672,10 +679,10 @@ __device__ __forceinline__ void mspread_body(V2<TG>* __restrict__ grid, long lon
     }
 }
 
-// (4 waves per SIMD: a bound of 5, which the LDS would admit, spills in the block loop and was
-// measured 30% slower)
+// (weight-table plans: 5 waves per SIMD, all that 16 KiB of LDS per workgroup admits, with one
+// product chain; the other variants keep 4)
 template <typename T, typename TG, int MSP, int DIM, int KC, bool BINS, bool WT>
-__global__ void __launch_bounds__(2 * KC, 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
+__global__ void __launch_bounds__(2 * KC, (WT && mspread_lds<KC, BINS>() <= 16384) ? 5 : 4) k_mspread(V2<TG>* __restrict__ grid, long long gstride,
                                                         const V2<T>* __restrict__ cbuf, long long cstride,
                                                         NodeArgs na, const GItem* __restrict__ items, int nitems,
                                                         const int* __restrict__ cand, double qq, BinArgs ba,
