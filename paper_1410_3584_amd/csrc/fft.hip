@@ -718,8 +718,9 @@ static int launch_cols(nlf_plan* p, ColsArgs a, int outer, int batch) {
             return launch_cols_r<T, DIR, LP, SP, 9>(p, a, outer, batch);
         if (a.n == 1024 && a.inner % cols_r_c<10>() == 0 && a.bc2 % cols_r_c<10>() == 0)
             return launch_cols_r<T, DIR, LP, SP, 10>(p, a, outer, batch);
-        // 64- to 256-point columns, where the blocks of C columns still fill the device
-        auto fills = [&](int c) { return !a.bc2 && a.inner % c == 0 && (a.inner / c) * outer * (long long)batch >= 256; };
+        // 64- to 256-point columns (also where the blocks of C columns do not fill the device: the
+        // LDS kernel below takes 4096 elements per workgroup, so it would have half as many)
+        auto fills = [&](int c) { return !a.bc2 && a.inner % c == 0; };
         if (a.n == 256 && fills(cols_r_c<8>())) return launch_cols_r<T, DIR, LP, SP, 8>(p, a, outer, batch);
         if (a.n == 128 && fills(cols_r_c<7>())) return launch_cols_r<T, DIR, LP, SP, 7>(p, a, outer, batch);
         if (a.n == 64 && fills(cols_r_c<6>())) return launch_cols_r<T, DIR, LP, SP, 6>(p, a, outer, batch);
